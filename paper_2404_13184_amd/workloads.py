@@ -1,0 +1,467 @@
+"""Seeded synthetic workloads: gate matrices, Kraus channels and circuit generators.
+
+This module is the single source of inputs for both the CPU reference (``oracle/``)
+and the HIP path.  It holds no superoperator arithmetic: it only emits an explicit,
+ordered list of operations, each a set of Kraus matrices acting on named qubits.
+A unitary gate is the one-element case (the problem statement of Sec. 2.1, Eq.
+``eq:dmsim``: the input is rho_in plus a sequence of not-necessarily-unitary
+transformations).
+
+Conventions (shared by every consumer):
+
+* A j-qubit matrix acting on ``qubits = (q_0, ..., q_{j-1})`` is indexed by the local
+  basis index ``sum_t b_{q_t} 2^t``: the first listed qubit is the least-significant
+  bit.  Matrices are ``M[out, in]``.
+* Qubit q of an n-qubit register is bit q of the row index of rho (little-endian), as
+  in the strided index map of Sec. 3.1, whose 2^q terms address qubit q.
+
+Noise channels follow the Qiskit-Aer conventions the paper adopts (Sec. 3.5):
+depolarizing with parameter p on j qubits is (1-p) rho + p Tr_Q(rho) (x) I/2^j,
+amplitude damping, phase damping, and thermal relaxation built from the two.
+"""
+from __future__ import annotations
+
+import dataclasses
+import itertools
+import math
+from typing import List, Sequence, Tuple
+
+import numpy as np
+
+# --------------------------------------------------------------------------------------
+# Operation record
+# --------------------------------------------------------------------------------------
+
+
+@dataclasses.dataclass(frozen=True)
+class Op:
+    """One circuit operation: Kraus matrices ``mats`` (m, 2^j, 2^j) on ``qubits``.
+
+    ``kind`` is ``"gate"`` for a unitary (m == 1) and ``"kraus"`` for a channel.
+    ``label`` is informational only (e.g. ``"u3"``, ``"dep1"``).
+    """
+
+    kind: str
+    qubits: Tuple[int, ...]
+    mats: np.ndarray
+    label: str = ""
+
+    @property
+    def width(self) -> int:
+        return len(self.qubits)
+
+
+def gate(U: np.ndarray, qubits: Sequence[int], label: str = "") -> Op:
+    U = np.asarray(U, dtype=np.complex128)
+    j = len(qubits)
+    assert U.shape == (2 ** j, 2 ** j)
+    return Op("gate", tuple(int(q) for q in qubits), U.reshape(1, 2 ** j, 2 ** j).copy(), label)
+
+
+def channel(kraus: Sequence[np.ndarray], qubits: Sequence[int], label: str = "") -> Op:
+    K = np.asarray(np.stack([np.asarray(k, dtype=np.complex128) for k in kraus]))
+    j = len(qubits)
+    assert K.shape[1:] == (2 ** j, 2 ** j)
+    return Op("kraus", tuple(int(q) for q in qubits), K, label)
+
+
+# --------------------------------------------------------------------------------------
+# Gate matrices
+# --------------------------------------------------------------------------------------
+
+I2 = np.eye(2, dtype=np.complex128)
+PX = np.array([[0, 1], [1, 0]], dtype=np.complex128)
+PY = np.array([[0, -1j], [1j, 0]], dtype=np.complex128)
+PZ = np.array([[1, 0], [0, -1]], dtype=np.complex128)
+PAULIS = {"I": I2, "X": PX, "Y": PY, "Z": PZ}
+
+
+def u3(theta: float, phi: float, lam: float) -> np.ndarray:
+    """OpenQASM 2 U3(theta, phi, lambda)."""
+    c, s = math.cos(theta / 2), math.sin(theta / 2)
+    return np.array(
+        [[c, -np.exp(1j * lam) * s], [np.exp(1j * phi) * s, np.exp(1j * (phi + lam)) * c]],
+        dtype=np.complex128,
+    )
+
+
+def rx(theta: float) -> np.ndarray:
+    """exp(-i theta X / 2)."""
+    c, s = math.cos(theta / 2), math.sin(theta / 2)
+    return np.array([[c, -1j * s], [-1j * s, c]], dtype=np.complex128)
+
+
+def rz(theta: float) -> np.ndarray:
+    """exp(-i theta Z / 2)."""
+    return np.diag([np.exp(-0.5j * theta), np.exp(0.5j * theta)]).astype(np.complex128)
+
+
+def hadamard() -> np.ndarray:
+    return np.array([[1, 1], [1, -1]], dtype=np.complex128) / math.sqrt(2.0)
+
+
+def rzz(theta: float) -> np.ndarray:
+    """exp(-i theta Z(x)Z / 2); diagonal, eigenvalue of ZZ is (-1)^(b0 xor b1)."""
+    d = []
+    for idx in range(4):
+        b0, b1 = idx & 1, (idx >> 1) & 1
+        zz = 1 - 2 * (b0 ^ b1)
+        d.append(np.exp(-0.5j * theta * zz))
+    return np.diag(d).astype(np.complex128)
+
+
+def controlled(U1: np.ndarray) -> np.ndarray:
+    """Two-qubit controlled-U on qubits (control, target): local index b_c + 2 b_t.
+
+    Defined by its action on basis states: if b_c == 1 the target's 2x2 block is U1.
+    """
+    M = np.zeros((4, 4), dtype=np.complex128)
+    for bc in range(2):
+        for bt_in in range(2):
+            col = bc + 2 * bt_in
+            if bc == 0:
+                M[col, col] = 1.0
+            else:
+                for bt_out in range(2):
+                    M[bc + 2 * bt_out, col] = U1[bt_out, bt_in]
+    return M
+
+
+def cx() -> np.ndarray:
+    return controlled(PX)
+
+
+def cz() -> np.ndarray:
+    return controlled(PZ)
+
+
+def swap() -> np.ndarray:
+    M = np.zeros((4, 4), dtype=np.complex128)
+    for b0 in range(2):
+        for b1 in range(2):
+            M[b1 + 2 * b0, b0 + 2 * b1] = 1.0
+    return M
+
+
+def random_unitary(rng: np.random.Generator, dim: int) -> np.ndarray:
+    """Haar-random unitary via QR of a complex Ginibre matrix (Mezzadri's phase fix)."""
+    z = (rng.standard_normal((dim, dim)) + 1j * rng.standard_normal((dim, dim))) / math.sqrt(2)
+    q, r = np.linalg.qr(z)
+    ph = np.diag(r) / np.abs(np.diag(r))
+    return q * ph
+
+
+# --------------------------------------------------------------------------------------
+# Noise channels (Kraus sets), Sec. 3.5
+# --------------------------------------------------------------------------------------
+
+
+def pauli_string_matrix(labels: str) -> np.ndarray:
+    """Matrix of a j-qubit Pauli string; ``labels[t]`` acts on local qubit t (bit t)."""
+    M = np.array([[1.0 + 0j]])
+    for ch in labels:  # local qubit t is bit t: it is the right-most Kronecker factor so far
+        M = np.kron(PAULIS[ch], M)
+    return M
+
+
+def depolarizing(p: float, j: int) -> List[np.ndarray]:
+    """Kraus set of (1-p) rho + p Tr_Q(rho) (x) I/2^j on j qubits (Qiskit-Aer convention).
+
+    Pauli-mixture form: identity with weight 1 - (4^j - 1) p / 4^j, every other Pauli
+    string with weight p / 4^j.
+    """
+    d4 = 4 ** j
+    if not (0.0 <= p <= d4 / (d4 - 1)):
+        raise ValueError("depolarizing parameter out of range")
+    out = []
+    for labels in itertools.product("IXYZ", repeat=j):
+        s = "".join(labels)
+        w = 1.0 - (d4 - 1) * p / d4 if set(s) == {"I"} else p / d4
+        if w > 0.0:
+            out.append(math.sqrt(w) * pauli_string_matrix(s))
+    return out
+
+
+def amplitude_damping(gamma: float) -> List[np.ndarray]:
+    k0 = np.array([[1, 0], [0, math.sqrt(1 - gamma)]], dtype=np.complex128)
+    k1 = np.array([[0, math.sqrt(gamma)], [0, 0]], dtype=np.complex128)
+    return [k0, k1]
+
+
+def phase_damping(lam: float) -> List[np.ndarray]:
+    k0 = np.array([[1, 0], [0, math.sqrt(1 - lam)]], dtype=np.complex128)
+    k1 = np.array([[0, 0], [0, math.sqrt(lam)]], dtype=np.complex128)
+    return [k0, k1]
+
+
+def thermal_relaxation(t1: float, t2: float, t: float) -> List[np.ndarray]:
+    """Thermal relaxation toward |0> (zero excited-state population), requires T2 <= 2 T1.
+
+    Populations relax as exp(-t/T1) and coherences as exp(-t/T2).  Built as amplitude
+    damping with gamma = 1 - exp(-t/T1) followed by phase damping with
+    lambda = 1 - exp(-2t/T2 + t/T1); the Kraus set is the non-zero products.
+    """
+    if t2 > 2 * t1:
+        raise ValueError("thermal_relaxation needs T2 <= 2 T1")
+    gamma = 1.0 - math.exp(-t / t1)
+    lam = 1.0 - math.exp(-2.0 * t / t2 + t / t1)
+    out = []
+    for P in phase_damping(lam):
+        for A in amplitude_damping(gamma):
+            K = P @ A
+            if np.abs(K).max() > 0:
+                out.append(K)
+    return out
+
+
+def dephase() -> List[np.ndarray]:
+    """Mid-circuit Z-basis measurement with the outcome discarded: complete dephasing."""
+    return [np.diag([1.0, 0.0]).astype(np.complex128), np.diag([0.0, 1.0]).astype(np.complex128)]
+
+
+# --------------------------------------------------------------------------------------
+# Circuit generators (seeded, PCG64)
+# --------------------------------------------------------------------------------------
+
+
+def _pairing(rng: np.random.Generator, n: int) -> List[Tuple[int, int]]:
+    perm = rng.permutation(n)
+    return [(int(perm[2 * i]), int(perm[2 * i + 1])) for i in range(n // 2)]
+
+
+def _rand_u3(rng: np.random.Generator) -> np.ndarray:
+    th, ph, la = rng.uniform(0.0, 2 * math.pi, size=3)
+    return u3(th, ph, la)
+
+
+def random_u3_cx(n: int, layers: int, seed: int, p1: float, p2: float,
+                 gamma: float | None = None) -> List[Op]:
+    """Layers of U3 on every qubit (+1q noise) then CX on a random disjoint pairing (+2q dep).
+
+    Each 1q gate is followed by depolarizing(p1) and, if ``gamma`` is given, amplitude
+    damping(gamma); each CX (control = first of the pair) by 2q depolarizing(p2).
+    """
+    rng = np.random.default_rng(seed)
+    ops: List[Op] = []
+    dep1 = depolarizing(p1, 1) if p1 > 0 else None
+    dep2 = depolarizing(p2, 2) if p2 > 0 else None
+    ad = amplitude_damping(gamma) if gamma else None
+    for _ in range(layers):
+        for q in range(n):
+            ops.append(gate(_rand_u3(rng), (q,), "u3"))
+            if dep1 is not None:
+                ops.append(channel(dep1, (q,), "dep1"))
+            if ad is not None:
+                ops.append(channel(ad, (q,), "ad"))
+        for c, t in _pairing(rng, n):
+            ops.append(gate(cx(), (c, t), "cx"))
+            if dep2 is not None:
+                ops.append(channel(dep2, (c, t), "dep2"))
+    return ops
+
+
+def config1(layers: int = 20, seed: int = 1, n: int = 8) -> Tuple[int, List[Op]]:
+    """8-qubit random U3/CX circuit, depth 20, dep 1e-3 + AD 5e-4 per 1q gate, dep2 1e-2."""
+    return n, random_u3_cx(n, layers, seed, 1e-3, 1e-2, gamma=5e-4)
+
+
+def brickwork_cz(n: int, layers: int, seed: int, p1: float, p2: float, lam: float) -> List[Op]:
+    """U3 on every qubit (+dep1 +PD) then CZ on even/odd nearest-neighbour bonds (+dep2 +PD)."""
+    rng = np.random.default_rng(seed)
+    dep1, dep2, pd = depolarizing(p1, 1), depolarizing(p2, 2), phase_damping(lam)
+    ops: List[Op] = []
+    for layer in range(layers):
+        for q in range(n):
+            ops.append(gate(_rand_u3(rng), (q,), "u3"))
+            ops.append(channel(dep1, (q,), "dep1"))
+            ops.append(channel(pd, (q,), "pd"))
+        for a in range(layer % 2, n - 1, 2):
+            ops.append(gate(cz(), (a, a + 1), "cz"))
+            ops.append(channel(dep2, (a, a + 1), "dep2"))
+            ops.append(channel(pd, (a,), "pd"))
+            ops.append(channel(pd, (a + 1,), "pd"))
+    return ops
+
+
+def config2(layers: int = 200, seed: int = 2, n: int = 14) -> Tuple[int, List[Op]]:
+    return n, brickwork_cz(n, layers, seed, 1e-3, 1e-2, 1e-3)
+
+
+def ising_trotter(n: int, steps: int, seed: int, J: float = 1.0, dt: float = 0.05,
+                  t1: float = 100.0, t2: float = 80.0, tg: float = 0.05,
+                  noisy: bool = True) -> Tuple[List[Op], np.ndarray]:
+    """Open-chain TFIM H = J sum Z_i Z_{i+1} + sum h_i X_i, first-order Trotter.
+
+    Each step: RZZ(2 J dt) on every bond then RX(2 h_i dt) on every qubit; h_i ~ U[0.5,1.5]
+    drawn once.  Thermal relaxation (T1, T2, gate time tg) follows every gate on each
+    qubit it touches.  Returns (ops, h).
+    """
+    rng = np.random.default_rng(seed)
+    h = rng.uniform(0.5, 1.5, size=n)
+    tr = thermal_relaxation(t1, t2, tg) if noisy else None
+    ops: List[Op] = []
+    for _ in range(steps):
+        for a in range(n - 1):
+            ops.append(gate(rzz(2 * J * dt), (a, a + 1), "rzz"))
+            if tr is not None:
+                ops.append(channel(tr, (a,), "tr"))
+                ops.append(channel(tr, (a + 1,), "tr"))
+        for q in range(n):
+            ops.append(gate(rx(2 * h[q] * dt), (q,), "rx"))
+            if tr is not None:
+                ops.append(channel(tr, (q,), "tr"))
+    return ops, h
+
+
+def config3(steps: int = 50, seed: int = 3, n: int = 15) -> Tuple[int, List[Op]]:
+    ops, _ = ising_trotter(n, steps, seed)
+    return n, ops
+
+
+def config4(layers: int = 100, seed: int = 4, n: int = 16) -> Tuple[int, List[Op]]:
+    return n, random_u3_cx(n, layers, seed, 1e-3, 1e-2)
+
+
+def teleport_block(a: int, b: int, c: int, U_in: np.ndarray, p1: float, p2: float) -> List[Op]:
+    """Teleport qubit a's state (prepared by U_in) onto c through the Bell pair (b, c).
+
+    H(b), CX(b,c); CX(a,b), H(a); Z-measurements of a and b modelled as dephasing;
+    corrections CX(b,c), CZ(a,c) (deferred-measurement form).  1q gates are followed by
+    depolarizing(p1), 2q gates by 2q depolarizing(p2) when the rates are positive.
+    """
+    d1 = depolarizing(p1, 1) if p1 > 0 else None
+    d2 = depolarizing(p2, 2) if p2 > 0 else None
+    ops: List[Op] = []
+
+    def g1(U, q, lab):
+        ops.append(gate(U, (q,), lab))
+        if d1 is not None:
+            ops.append(channel(d1, (q,), "dep1"))
+
+    def g2(U, q0, q1, lab):
+        ops.append(gate(U, (q0, q1), lab))
+        if d2 is not None:
+            ops.append(channel(d2, (q0, q1), "dep2"))
+
+    g1(U_in, a, "u3")
+    g1(hadamard(), b, "h")
+    g2(cx(), b, c, "cx")
+    g2(cx(), a, b, "cx")
+    g1(hadamard(), a, "h")
+    ops.append(channel(dephase(), (a,), "meas"))
+    ops.append(channel(dephase(), (b,), "meas"))
+    g2(cx(), b, c, "cx")
+    g2(cz(), a, c, "cz")
+    return ops
+
+
+def teleport_layers(n: int, layers: int, seed: int, p1: float, p2: float) -> List[Op]:
+    """Layers of teleport blocks on a random disjoint set of qubit triples."""
+    rng = np.random.default_rng(seed)
+    ops: List[Op] = []
+    for _ in range(layers):
+        perm = rng.permutation(n)
+        for i in range(n // 3):
+            a, b, c = (int(x) for x in perm[3 * i:3 * i + 3])
+            ops.extend(teleport_block(a, b, c, _rand_u3(rng), p1, p2))
+    return ops
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    arrival_s: float
+    n: int
+    kind: str
+    depth: int
+    p1: float
+    ops: List[Op]
+
+
+def config5(num_requests: int = 5000, rate_hz: float = 200.0, seed: int = 5,
+            n_range: Tuple[int, int] = (4, 12), depth_range: Tuple[int, int] = (20, 200)
+            ) -> List[Request]:
+    """Serving stream: Poisson arrivals; n ~ U{4..12}; depth ~ U{20..200}; mixed types.
+
+    Types: random U3/CX (depth = layers), Ising Trotter (depth = Trotter steps) and
+    teleport blocks (depth = layers of triples; n >= 3).  p1 ~ U[1e-4, 1e-2], p2 = 10 p1.
+    Circuits are generated lazily by :func:`request_ops` from the per-request seed.
+    """
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate_hz, size=num_requests)
+    t = np.cumsum(gaps)
+    out = []
+    kinds = ("u3cx", "ising", "teleport")
+    for i in range(num_requests):
+        n = int(rng.integers(n_range[0], n_range[1] + 1))
+        depth = int(rng.integers(depth_range[0], depth_range[1] + 1))
+        kind = kinds[int(rng.integers(0, 3))]
+        p1 = float(rng.uniform(1e-4, 1e-2))
+        out.append(Request(i, float(t[i]), n, kind, depth, p1, []))
+    return out
+
+
+def request_ops(req: Request, seed_base: int = 1000) -> List[Op]:
+    seed = seed_base + req.rid
+    p1, p2 = req.p1, min(10 * req.p1, 0.5)
+    if req.kind == "u3cx":
+        return random_u3_cx(req.n, req.depth, seed, p1, p2)
+    if req.kind == "ising":
+        # thermal relaxation scaled so the per-gate error is of order p1
+        t1 = 0.05 / p1
+        ops, _ = ising_trotter(req.n, req.depth, seed, t1=t1, t2=t1, tg=0.05)
+        return ops
+    if req.kind == "teleport":
+        return teleport_layers(req.n, req.depth, seed, p1, p2)
+    raise ValueError(req.kind)
+
+
+def zz_paulis(n: int) -> List[str]:
+    """Pauli strings <Z_i Z_{i+1}> for i = 0..n-2 (character t acts on qubit t)."""
+    out = []
+    for i in range(n - 1):
+        s = ["I"] * n
+        s[i] = s[i + 1] = "Z"
+        out.append("".join(s))
+    return out
+
+
+def z_paulis(n: int) -> List[str]:
+    out = []
+    for i in range(n):
+        s = ["I"] * n
+        s[i] = "Z"
+        out.append("".join(s))
+    return out
+
+
+# --------------------------------------------------------------------------------------
+# Counter-based input generator (SplitMix64, Steele, Lea & Flood, OOPSLA 2014)
+# --------------------------------------------------------------------------------------
+
+_M64 = (1 << 64) - 1
+
+
+def splitmix64(x: np.ndarray) -> np.ndarray:
+    """SplitMix64 finaliser applied to counters ``x`` (uint64 array): returns uint64."""
+    z = (x.astype(np.uint64) + np.uint64(0x9E3779B97F4A7C15)) & np.uint64(_M64)
+    z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+    z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+    return z ^ (z >> np.uint64(31))
+
+
+def hash_fill_values(seed: int, index: np.ndarray) -> np.ndarray:
+    """Pseudo-random complex value at vec index ``index`` for the seeded fill.
+
+    re = u(2*(seed*2^40 + index)), im = u(2*(seed*2^40 + index) + 1), u(c) = the top 53 bits
+    of splitmix64(c) as a double in [-0.5, 0.5).  The device fill implements the same
+    definition independently.
+    """
+    with np.errstate(over="ignore"):
+        idx = np.asarray(index, dtype=np.uint64)
+        base = (np.uint64(seed) << np.uint64(40)) + idx
+        c0 = base * np.uint64(2)
+        c1 = c0 + np.uint64(1)
+        r0 = (splitmix64(c0) >> np.uint64(11)).astype(np.float64) * (2.0 ** -53) - 0.5
+        r1 = (splitmix64(c1) >> np.uint64(11)).astype(np.float64) * (2.0 ** -53) - 0.5
+    return r0 + 1j * r1

@@ -1,0 +1,474 @@
+"""Pins for the CPU FP64 reference (runs without a GPU).
+
+Each check ties the oracle to something other than itself:
+
+* brute force: full 2^n x 2^n Kraus operators by Kronecker products and an explicit qubit
+  permutation, full 4^n x 4^n superoperators sum conj(F) (x) F (Sec. 3.1: vec(A B C) =
+  (C^T (x) A) vec(B)), multiplied and applied to vec(rho_in);
+* the paper's strided index map for one-qubit superoperators (Sec. 3.1, the s_i equation);
+* closed forms of the noise channels, Bell and teleportation fidelities, the ideal
+  teleportation chi matrix (Sec. 5, case study 1), TFIM limits;
+* invariants (trace, Hermiticity, positivity, purity) and the pure-state special case;
+* planted mistakes: mutated copies of the oracle source must fail these pins.
+"""
+import itertools
+import math
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_2404_13184_amd import workloads as W
+
+TOL = 1e-13
+
+
+# ------------------------------------------------------------------------------------
+# brute-force Kronecker construction (independent of the oracle's row/column passes)
+# ------------------------------------------------------------------------------------
+
+def full_operator(K, qubits, n):
+    """2^n x 2^n operator of K on ``qubits`` (identity elsewhere) via kron + permutation."""
+    j = len(qubits)
+    D = 1 << j
+    rest = [q for q in range(n) if q not in qubits]
+    big = np.kron(np.eye(1 << (n - j)), K)  # layout: targets in the low bits, rest above
+    perm = np.zeros((1 << n, 1 << n))
+    for x in range(1 << n):
+        a = sum(((x >> q) & 1) << t for t, q in enumerate(qubits))
+        b = sum(((x >> r) & 1) << s for s, r in enumerate(rest))
+        perm[a + D * b, x] = 1.0
+    return perm.T @ big @ perm
+
+
+def brute_superop(op, n):
+    S = np.zeros((4 ** n, 4 ** n), dtype=np.complex128)
+    for K in op.mats:
+        F = full_operator(K, op.qubits, n)
+        S += np.kron(F.conj(), F)
+    return S
+
+
+def brute_run(n, ops, rho_in):
+    v = rho_in.T.reshape(-1).astype(np.complex128)  # column stacking
+    for op in ops:
+        v = brute_superop(op, n) @ v
+    return v.reshape(1 << n, 1 << n).T
+
+
+def random_density(rng, n, rank=None):
+    dim = 1 << n
+    rank = rank or dim
+    A = rng.standard_normal((dim, rank)) + 1j * rng.standard_normal((dim, rank))
+    rho = A @ A.conj().T
+    return rho / np.trace(rho)
+
+
+def random_matrix(rng, dim):
+    return rng.standard_normal((dim, dim)) + 1j * rng.standard_normal((dim, dim))
+
+
+def random_ops(rng, n, count, widths=(1, 2, 3)):
+    ops = []
+    for _ in range(count):
+        j = int(rng.choice([w for w in widths if w <= n]))
+        qs = tuple(int(x) for x in rng.choice(n, size=j, replace=False))
+        kind = rng.integers(0, 3)
+        if kind == 0:
+            ops.append(W.gate(W.random_unitary(rng, 1 << j), qs))
+        elif kind == 1:
+            ops.append(W.channel(W.depolarizing(float(rng.uniform(0, 0.3)), j), qs))
+        else:  # arbitrary (non trace preserving) Kraus set: linearity holds for any K
+            ops.append(W.channel([random_matrix(rng, 1 << j) * 0.5 for _ in range(int(rng.integers(1, 4)))], qs))
+    return ops
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4])
+def test_bruteforce_random_circuits(oracle_mod, n):
+    rng = np.random.default_rng(100 + n)
+    for trial in range(3):
+        ops = random_ops(rng, n, 6)
+        rho = random_density(rng, n)
+        got = oracle_mod.run(n, ops, rho)
+        want = brute_run(n, ops, rho)
+        assert np.abs(got - want).max() <= TOL * max(1.0, np.abs(want).max())
+
+
+def test_bruteforce_every_placement(oracle_mod):
+    """Every ordered placement of 1-, 2- and 3-qubit operators on n = 4."""
+    n = 4
+    rng = np.random.default_rng(7)
+    for j in (1, 2, 3):
+        for qs in itertools.permutations(range(n), j):
+            op = W.channel([random_matrix(rng, 1 << j), random_matrix(rng, 1 << j)], qs)
+            rho = random_matrix(rng, 1 << n)  # non-Hermitian input: the map is linear
+            got = oracle_mod.run(n, [op], rho)
+            want = brute_run(n, [op], rho)
+            assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max(), (j, qs)
+
+
+def test_bruteforce_workload_channels(oracle_mod):
+    """The physical channels of the workloads, against brute force."""
+    n = 3
+    rng = np.random.default_rng(11)
+    chans = [
+        W.channel(W.depolarizing(0.2, 1), (1,)),
+        W.channel(W.depolarizing(0.3, 2), (2, 0)),
+        W.channel(W.amplitude_damping(0.37), (0,)),
+        W.channel(W.phase_damping(0.21), (2,)),
+        W.channel(W.thermal_relaxation(1.0, 0.7, 0.3), (1,)),
+        W.channel(W.dephase(), (0,)),
+        W.gate(W.cx(), (2, 1)),
+        W.gate(W.cz(), (0, 2)),
+        W.gate(W.rzz(0.7), (1, 2)),
+        W.gate(W.u3(0.3, 1.1, -0.4), (1,)),
+        W.gate(W.rx(0.9), (0,)),
+        W.gate(W.swap(), (0, 1)),
+    ]
+    rho = random_density(rng, n)
+    got = oracle_mod.run(n, chans, rho)
+    want = brute_run(n, chans, rho)
+    assert np.abs(got - want).max() <= TOL
+
+
+# ------------------------------------------------------------------------------------
+# the paper's strided index map (Sec. 3.1)
+# ------------------------------------------------------------------------------------
+
+def paper_s(i, q, n):
+    """s_i of Sec. 3.1 for a one-qubit gate on qubit q of an n-qubit register."""
+    hi = i >> q
+    return (hi // (1 << (n - 1))) * (1 << (q + n + 1)) + (hi % (1 << (n - 1))) * (1 << (q + 1)) + (i % (1 << q))
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4])
+def test_paper_index_map_partitions(n):
+    for q in range(n):
+        seen = np.zeros(4 ** n, dtype=int)
+        for i in range(4 ** (n - 1)):
+            s = paper_s(i, q, n)
+            for o in (0, 1 << q, 1 << (q + n), (1 << q) + (1 << (q + n))):
+                seen[s + o] += 1
+        assert (seen == 1).all(), (n, q)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3])
+def test_paper_index_map_update_matches_oracle(oracle_mod, n):
+    """Updating the groups {s_i, s_i+2^q, s_i+2^(q+n), s_i+2^q+2^(q+n)} of vec(rho) with the
+    4x4 superoperator sum_i conj(K_i) (x) K_i equals sum_i K_i rho K_i^dag."""
+    rng = np.random.default_rng(5 + n)
+    for q in range(n):
+        Ks = [random_matrix(rng, 2) for _ in range(3)]
+        S4 = sum(np.kron(K.conj(), K) for K in Ks)
+        rho = random_matrix(rng, 1 << n)
+        v = rho.T.reshape(-1).copy()
+        for i in range(4 ** (n - 1)):
+            s = paper_s(i, q, n)
+            idx = [s, s + (1 << q), s + (1 << (q + n)), s + (1 << q) + (1 << (q + n))]
+            v[idx] = S4 @ v[idx]
+        got = oracle_mod.run(n, [W.channel(Ks, (q,))], rho)
+        assert np.abs(v.reshape(1 << n, 1 << n).T - got).max() <= 1e-12 * np.abs(got).max()
+
+
+# ------------------------------------------------------------------------------------
+# closed forms
+# ------------------------------------------------------------------------------------
+
+def bloch(oracle_mod, rho, n=1, q=0):
+    out = []
+    for P in "XYZ":
+        s = ["I"] * n
+        s[q] = P
+        out.append(oracle_mod.expect_pauli(rho, "".join(s)).real)
+    return np.array(out)
+
+
+def test_depolarizing_bloch_shrink(oracle_mod):
+    p = 0.013
+    ops0 = [W.gate(W.u3(1.1, 0.4, 2.0), (0,))]
+    r0 = bloch(oracle_mod, oracle_mod.run(1, ops0))
+    for m in (1, 2, 7):
+        rho = oracle_mod.run(1, ops0 + [W.channel(W.depolarizing(p, 1), (0,))] * m)
+        assert np.abs(bloch(oracle_mod, rho) - (1 - p) ** m * r0).max() <= TOL
+        assert abs(np.trace(rho) - 1) <= TOL
+
+
+def test_depolarizing_two_qubit_paulis_shrink(oracle_mod):
+    p = 0.05
+    rng = np.random.default_rng(3)
+    prep = [W.gate(W.random_unitary(rng, 4), (0, 1))]
+    rho0 = oracle_mod.run(2, prep)
+    rho1 = oracle_mod.run(2, prep + [W.channel(W.depolarizing(p, 2), (0, 1))])
+    for a, b in itertools.product("IXYZ", repeat=2):
+        s = a + b
+        e0 = oracle_mod.expect_pauli(rho0, s)
+        e1 = oracle_mod.expect_pauli(rho1, s)
+        want = e0 if s == "II" else (1 - p) * e0
+        assert abs(e1 - want) <= TOL
+
+
+def test_depolarizing_fixed_point(oracle_mod):
+    mixed = np.eye(2, dtype=np.complex128) / 2
+    out = oracle_mod.run(1, [W.channel(W.depolarizing(0.3, 1), (0,))], mixed)
+    assert np.abs(out - mixed).max() <= TOL
+    rho = oracle_mod.run(1, [W.gate(W.u3(0.3, 0.2, 0.1), (0,)), W.channel(W.depolarizing(1.0, 1), (0,))])
+    assert np.abs(rho - mixed).max() <= TOL
+    rho2 = oracle_mod.run(2, [W.gate(W.cx(), (0, 1)), W.channel(W.depolarizing(1.0, 2), (0, 1))],
+                          random_density(np.random.default_rng(1), 2))
+    assert np.abs(rho2 - np.eye(4) / 4).max() <= TOL
+
+
+def test_amplitude_damping_decay(oracle_mod):
+    g = 0.07
+    prep = [W.gate(W.u3(2.1, 0.3, 0.0), (0,))]
+    rho0 = oracle_mod.run(1, prep)
+    for m in (1, 3, 10):
+        rho = oracle_mod.run(1, prep + [W.channel(W.amplitude_damping(g), (0,))] * m)
+        assert abs(rho[1, 1] - rho0[1, 1] * (1 - g) ** m) <= TOL
+        assert abs(rho[0, 1] - rho0[0, 1] * (1 - g) ** (m / 2)) <= TOL
+    rho = oracle_mod.run(1, prep + [W.channel(W.amplitude_damping(1.0), (0,))])
+    assert np.abs(rho - np.diag([1.0, 0.0])).max() <= TOL
+
+
+def test_phase_damping_decay(oracle_mod):
+    lam = 0.11
+    prep = [W.gate(W.u3(1.0, 0.7, 0.2), (0,))]
+    rho0 = oracle_mod.run(1, prep)
+    for m in (1, 4):
+        rho = oracle_mod.run(1, prep + [W.channel(W.phase_damping(lam), (0,))] * m)
+        assert abs(rho[0, 1] - rho0[0, 1] * (1 - lam) ** (m / 2)) <= TOL
+        assert abs(rho[0, 0] - rho0[0, 0]) <= TOL and abs(rho[1, 1] - rho0[1, 1]) <= TOL
+
+
+def test_thermal_relaxation_decay(oracle_mod):
+    t1, t2, t = 100.0, 80.0, 0.05
+    # one-step factors at the Ising workload's parameters
+    assert abs(math.exp(-t / t1) - 0.99950012) < 1e-8
+    assert abs(math.exp(-t / t2) - 0.99937520) < 1e-8
+    prep = [W.gate(W.u3(1.3, 0.5, 0.9), (0,))]
+    rho0 = oracle_mod.run(1, prep)
+    for m in (1, 5):
+        rho = oracle_mod.run(1, prep + [W.channel(W.thermal_relaxation(t1, t2, t), (0,))] * m)
+        assert abs(rho[1, 1] - rho0[1, 1] * math.exp(-m * t / t1)) <= TOL
+        assert abs(rho[0, 1] - rho0[0, 1] * math.exp(-m * t / t2)) <= TOL
+
+
+PHI_PLUS = np.array([1, 0, 0, 1], dtype=np.complex128) / math.sqrt(2)
+
+
+def test_bell_fidelity(oracle_mod):
+    bell = [W.gate(W.hadamard(), (0,)), W.gate(W.cx(), (0, 1))]
+    rho = oracle_mod.run(2, bell)
+    assert abs(PHI_PLUS.conj() @ rho @ PHI_PLUS - 1) <= TOL
+    for p in (0.01, 0.2):
+        rho = oracle_mod.run(2, bell + [W.channel(W.depolarizing(p, 2), (0, 1))])
+        assert abs((PHI_PLUS.conj() @ rho @ PHI_PLUS).real - (1 - 3 * p / 4)) <= TOL
+
+
+def partial_trace_keep(rho, n, keep):
+    """Reduced density matrix of qubit ``keep`` (qubit q = bit q of the index)."""
+    out = np.zeros((2, 2), dtype=np.complex128)
+    for a in range(2):
+        for b in range(2):
+            s = 0
+            for rest in range(1 << (n - 1)):
+                x = 0
+                r = rest
+                for q in range(n):
+                    if q == keep:
+                        continue
+                    x |= (r & 1) << q
+                    r >>= 1
+                s += rho[x | (a << keep), x | (b << keep)]
+            out[a, b] = s
+    return out
+
+
+def test_teleportation_fidelity(oracle_mod):
+    rng = np.random.default_rng(9)
+    for _ in range(3):
+        U = W.random_unitary(rng, 2)
+        psi = U[:, 0]
+        rho = oracle_mod.run(3, W.teleport_block(0, 1, 2, U, 0.0, 0.0))
+        out = partial_trace_keep(rho, 3, 2)
+        assert abs((psi.conj() @ out @ psi) - 1) <= 1e-12
+        # depolarizing p on the receiving half after the Bell preparation: F = 1 - p/2
+        p = 0.08
+        ops = W.teleport_block(0, 1, 2, U, 0.0, 0.0)
+        ops.insert(3, W.channel(W.depolarizing(p, 1), (2,)))  # after H(b), CX(b,c)
+        rho = oracle_mod.run(3, ops)
+        out = partial_trace_keep(rho, 3, 2)
+        assert abs((psi.conj() @ out @ psi).real - (1 - p / 2)) <= 1e-12
+
+
+def chi_matrix_of(oracle_mod, ops, n, src, dst):
+    """Process matrix chi (Pauli basis I, X, Y, Z) of the channel src -> dst, all other
+    qubits starting in |0>: E(rho) = sum_ij chi_ij sigma_i rho sigma_j."""
+    sig = [W.I2, W.PX, W.PY, W.PZ]
+    rows, rhs = [], []
+    for a in range(2):
+        for b in range(2):
+            Eab = np.zeros((2, 2), dtype=np.complex128)
+            Eab[a, b] = 1
+            rho_in = np.zeros((1 << n, 1 << n), dtype=np.complex128)
+            rho_in[a << src, b << src] = 1
+            out = partial_trace_keep(oracle_mod.run(n, ops, rho_in), n, dst)
+            for r in range(2):
+                for c in range(2):
+                    rows.append([(sig[i] @ Eab @ sig[j])[r, c] for i in range(4) for j in range(4)])
+                    rhs.append(out[r, c])
+    chi = np.linalg.solve(np.array(rows), np.array(rhs))
+    return chi.reshape(4, 4)
+
+
+def test_ideal_teleportation_chi_golden(oracle_mod):
+    golden = os.path.join(os.path.dirname(__file__), "golden", "teleport_chi_ideal.txt")
+    want = np.loadtxt(golden, comments="#").reshape(4, 4)
+    ops = W.teleport_block(0, 1, 2, W.I2, 0.0, 0.0)
+    chi = chi_matrix_of(oracle_mod, ops, 3, 0, 2)
+    assert np.abs(chi - want).max() <= 1e-12
+
+
+def test_tfim_limits(oracle_mod):
+    n = 4
+    # h = 0: |0..0> is a ZZ eigenstate and the relaxation fixed point, so <Z_i> = 1
+    ops, _ = W.ising_trotter(n, 3, seed=1)
+    ops_h0 = [op if op.label != "rx" else W.gate(W.rx(0.0), op.qubits, "rx") for op in ops]
+    rho = oracle_mod.run(n, ops_h0)
+    for s in W.z_paulis(n):
+        assert abs(oracle_mod.expect_pauli(rho, s) - 1) <= TOL
+    # J = 0: product of independent single-qubit evolutions
+    # drop each RZZ and the relaxation attached to it, so each qubit sees RX, TR per step
+    ops_j0 = []
+    skip = 0
+    for op in ops:
+        if op.label == "rzz":
+            skip = 2
+            continue
+        if skip and op.label == "tr":
+            skip -= 1
+            continue
+        ops_j0.append(op)
+    rho = oracle_mod.run(n, ops_j0)
+    prod = np.array([[1.0 + 0j]])
+    for q in range(n):
+        local = [type(op)(op.kind, (0,), op.mats, op.label) for op in ops_j0 if op.qubits == (q,)]
+        prod = np.kron(oracle_mod.run(1, local), prod)
+    assert np.abs(rho - prod).max() <= TOL
+
+
+# ------------------------------------------------------------------------------------
+# invariants and the pure-state special case
+# ------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,layers", [(4, 6), (6, 4)])
+def test_invariants_noisy(oracle_mod, n, layers):
+    _, ops = W.config1(layers=layers, n=n)
+    rho = oracle_mod.run(n, ops)
+    assert abs(np.trace(rho) - 1) <= TOL
+    assert np.abs(rho - rho.conj().T).max() <= 1e-14
+    assert np.linalg.eigvalsh(rho).min() >= -1e-12
+    assert np.trace(rho @ rho).real < 1 - 1e-6  # noise makes it mixed
+
+
+@pytest.mark.parametrize("n", [3, 6])
+def test_noiseless_matches_statevector(oracle_mod, n):
+    ops = W.random_u3_cx(n, 5, seed=21, p1=0.0, p2=0.0)
+    rho = oracle_mod.run(n, ops)
+    psi = oracle_mod.statevector(n, ops)
+    assert np.abs(rho - np.outer(psi, psi.conj())).max() <= 1e-13
+    assert abs(np.trace(rho @ rho) - 1) <= 1e-12
+
+
+def test_statevector_against_kron(oracle_mod):
+    rng = np.random.default_rng(2)
+    n = 4
+    for qs in [(0,), (3,), (1, 3), (3, 0), (2, 0, 3)]:
+        U = W.random_unitary(rng, 1 << len(qs))
+        psi0 = rng.standard_normal(16) + 1j * rng.standard_normal(16)
+        got = oracle_mod.statevector(n, [W.gate(U, qs)], psi0)
+        want = full_operator(U, qs, n) @ psi0
+        assert np.abs(got - want).max() <= 1e-13
+
+
+def test_expect_pauli_against_kron(oracle_mod):
+    rng = np.random.default_rng(4)
+    n = 3
+    rho = random_matrix(rng, 8)
+    for labels in itertools.product("IXYZ", repeat=n):
+        s = "".join(labels)
+        P = np.array([[1.0 + 0j]])
+        for ch in s:  # character t acts on qubit t = bit t
+            P = np.kron(W.PAULIS[ch], P)
+        want = np.trace(P @ rho)
+        assert abs(oracle_mod.expect_pauli(rho, s) - want) <= 1e-13
+
+
+def test_diag_and_trace(oracle_mod):
+    rng = np.random.default_rng(8)
+    rho = random_density(rng, 3)
+    p, tr = oracle_mod.diag(rho)
+    assert abs(tr - 1) <= TOL and np.abs(p - np.diag(rho).real).max() == 0
+
+
+def test_sample_block_matches_full(oracle_mod):
+    """The per-group definition used for full-size sampling agrees with a full run."""
+    rng = np.random.default_rng(12)
+    n = 5
+    ops = [W.gate(W.random_unitary(rng, 4), (3, 1)), W.channel(W.depolarizing(0.1, 1), (1,)),
+           W.channel(W.amplitude_damping(0.2), (3,))]
+    rho = random_matrix(rng, 1 << n)
+    vec = oracle_mod.matrix_to_vec(rho)
+    full = oracle_mod.run(n, ops, rho)
+    for rf, cf in [(0, 0), (0b10101 & ~0b01010, 0b00100), (0b00001, 0b10100)]:
+        Q, M_in, M_out = oracle_mod.sample_block(lambda idx: vec[idx], n, ops, rf, cf)
+        dep = [sum(((a >> t) & 1) << Q[t] for t in range(len(Q))) for a in range(1 << len(Q))]
+        want = full[np.ix_([rf + d for d in dep], [cf + d for d in dep])]
+        assert np.abs(M_out - want).max() <= 1e-13
+
+
+# ------------------------------------------------------------------------------------
+# planted mistakes: each mutation of the oracle source must fail a pin
+# ------------------------------------------------------------------------------------
+
+MUTATIONS = {
+    "dropped_conjugate": ("const double kr = K[2 * (b * D + a)], ki = -K[2 * (b * D + a) + 1];",
+                          "const double kr = K[2 * (b * D + a)], ki = K[2 * (b * D + a) + 1];"),
+    "transposed_K": ("const double kr = K[2 * (b * D + a)], ki = K[2 * (b * D + a) + 1];",
+                     "const double kr = K[2 * (a * D + b)], ki = K[2 * (a * D + b) + 1];"),
+    "sign_error": ("sr += kr * xr - ki * xi;", "sr += kr * xr + ki * xi;"),
+    "dropped_kraus_terms": ("for (int i = 0; i < m; ++i) {", "for (int i = 0; i < 1; ++i) {"),
+    "wrong_deposit": ("if ((a >> t) & 1u) r |= (uint64_t)1 << q[t];", "if ((a >> t) & 1u) r |= (uint64_t)1 << t;"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_planted_mistake_is_caught(oracle_mod, tmp_path, name, monkeypatch):
+    src = open(os.path.join(os.path.dirname(oracle_mod.library_path()), "oracle.c")).read()
+    old, new = MUTATIONS[name]
+    assert src.count(old) >= 1, name
+    mutated = src.replace(old, new, 1)
+    c = tmp_path / "m.c"
+    so = tmp_path / "m.so"
+    c.write_text(mutated)
+    subprocess.check_call(["gcc", "-O1", "-std=c99", "-fopenmp", "-fPIC", "-shared", str(c), "-o", str(so)])
+    import oracle.oracle as O
+
+    saved = O._lib
+    try:
+        O._lib = None
+        monkeypatch.setattr(O, "_LIB", str(so))
+        caught = False
+        rng = np.random.default_rng(31)
+        n = 3
+        for _ in range(2):
+            ops = random_ops(rng, n, 5)
+            rho = random_matrix(rng, 1 << n)
+            got = O.run(n, ops, rho)
+            want = brute_run(n, ops, rho)
+            if np.abs(got - want).max() > 1e-9 * np.abs(want).max():
+                caught = True
+        assert caught, name
+    finally:
+        O._lib = saved
