@@ -1,0 +1,209 @@
+"""Benchmark: 16-qubit density-matrix superoperator applies/s on one MI355X.
+
+Workload: the 16-qubit noisy random circuit (2^32-element vec(rho): 64 GiB in FP64,
+32 GiB in FP32), depth 100, each layer U3 on every qubit + 1q depolarizing(1e-3), then CX
+on a random disjoint pairing + 2q depolarizing(1e-2); seeded, synthetic.
+
+One step = the whole hot path on that circuit: reset rho to |0..0><0..0|, fuse the
+circuit (GPU superoperator construction + FP64 composition + packing), apply every fused
+superoperator, and reduce the 2^16 probabilities in FP64.  `value` = fused superoperator
+applies per second over the timed FP64 steps; FP32 is reported beside it.
+
+Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--layers", type=int, default=100)
+    ap.add_argument("--n", type=int, default=16)
+    ap.add_argument("--width", type=int, default=0, help="fusion width: 0 = autotuned, 2, 3, -1 none")
+    ap.add_argument("--precs", default="f64,f32")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-n", type=int, default=12)
+    ap.add_argument("--cpu-budget-s", type=float, default=20.0)
+    return ap.parse_args()
+
+
+def run_precision(T, W, torch, n, ops, prec, width, steps, warmup):
+    """Time `steps` full passes; returns a dict of measurements."""
+    stream = torch.cuda.current_stream()
+    circ = T.Circuit(n, ops)
+    d = T.DM(n, prec, stream)
+    dim = 1 << n
+
+    def one_step(events=None):
+        d.reset()
+        f = circ.fuse(width, prec, stream)
+        if events is None:
+            d.apply_fused(f)
+        else:
+            for i in range(f.count):
+                ev0 = torch.cuda.Event(enable_timing=True)
+                ev1 = torch.cuda.Event(enable_timing=True)
+                ev0.record(stream)
+                d.apply_fused(f, i, i + 1)
+                ev1.record(stream)
+                events.append((f.get_k(i), ev0, ev1))
+        p, tr = d.probs(renormalize=True)
+        info = f.info
+        f.free()
+        return info, p, tr
+
+    for _ in range(warmup):
+        one_step()
+    torch.cuda.synchronize()
+    events = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        info, p, tr = one_step(events)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per_k = {}
+    for k, e0, e1 in events:
+        per_k.setdefault(k, []).append(e0.elapsed_time(e1) * 1e-3)
+    d.free()
+    circ.free()
+    applies = info["count"] * steps
+    return {"wall_s": wall, "applies": applies, "info": info, "per_k": per_k, "trace": tr,
+            "pmax": float(p.max()), "pmin": float(p.min())}
+
+
+def roofline(prec, k, n, secs):
+    es = 16 if prec == "f64" else 8
+    nbytes = 2.0 * (4 ** n) * es
+    flops = 8.0 * (4 ** k) * (4 ** n)
+    peak_f = FP64_PEAK_TFLOPS if prec == "f64" else FP32_PEAK_TFLOPS
+    t_mem = nbytes / (HBM_PEAK_GBS * 1e9)
+    t_cmp = flops / (peak_f * 1e12)
+    if t_mem >= t_cmp:
+        ach = nbytes / secs / 1e9
+        return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel_k": k,
+                "avg_launch_ms": round(secs * 1e3, 3), "algorithmic_bytes": nbytes}
+    ach = flops / secs / 1e12
+    return {"bound": "mfma", "achieved": round(ach, 2), "peak": peak_f, "unit": "TFLOP/s",
+            "frac": round(ach / peak_f, 4), "traffic": None, "kernel_k": k,
+            "avg_launch_ms": round(secs * 1e3, 3), "algorithmic_flops": flops,
+            "hbm_GBs": round(nbytes / secs / 1e9, 1)}
+
+
+def cpu_baseline(W, n_full, layers_full, cpu_n, budget_s):
+    """The oracle (unfused FP64 sum K rho K^dag, all host threads) on a bounded sample of
+    the same circuit family at cpu_n qubits, scaled by 4^(n_full - cpu_n) to the 16-qubit
+    unit; returns gates/s and the equivalent applies/s."""
+    import oracle
+
+    oracle.build(force=False)
+    n_c, ops = W.config4(layers=layers_full, n=cpu_n)
+    rho = None
+    import numpy as np
+
+    rho = np.zeros((1 << cpu_n, 1 << cpu_n), dtype=np.complex128)
+    rho[0, 0] = 1.0
+    t0 = time.perf_counter()
+    done = 0
+    for op in ops:
+        oracle.run_on(rho, [op])
+        done += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    secs = time.perf_counter() - t0
+    gates_per_s_small = done / secs
+    scale = 4.0 ** (n_full - cpu_n)
+    return {"gates_per_s_16q_equiv": gates_per_s_small / scale, "ops_done": done, "secs": secs,
+            "cores": oracle.max_threads(), "cpu_n": cpu_n}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print("bench.py runs on one GPU only: this path has no multi-GPU sharding (use --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2404_13184_amd import tanq as T
+    from paper_2404_13184_amd import workloads as W
+
+    T.load()
+    torch.cuda.init()
+    n, ops = W.config4(layers=a.layers, n=a.n)
+    results = {}
+    for prec in a.precs.split(","):
+        results[prec] = run_precision(T, W, torch, n, ops, prec, a.width, a.steps, a.warmup)
+
+    main_prec = "f64" if "f64" in results else a.precs.split(",")[0]
+    r = results[main_prec]
+    value = r["applies"] / r["wall_s"]
+
+    def dominant(rr, prec):
+        k = max(rr["per_k"], key=lambda kk: sum(rr["per_k"][kk]))
+        secs = sum(rr["per_k"][k]) / len(rr["per_k"][k])
+        return roofline(prec, k, n, secs)
+
+    out = {
+        "metric": "16-qubit DM superop applies/s",
+        "value": round(value, 3),
+        "unit": "applies/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(r["wall_s"] / a.steps * 1e3, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": main_prec,
+        "data": "synthetic",
+        "config": {"workload": "16-qubit noisy random U3/CX circuit, depth 100, dep 1e-3/1e-2 "
+                               "(2^32-element vec(rho), %s)" % ("64 GiB FP64" if main_prec == "f64" else "32 GiB FP32"),
+                   "n_qubits": n, "layers": a.layers, "source_ops": len(ops),
+                   "fused_applies_per_step": r["info"]["count"], "fusion_width": r["info"]["max_width"],
+                   "count_by_k": r["info"]["count_k"][1:]},
+        "gates_per_s": round(len(ops) * a.steps / r["wall_s"], 1),
+        "roofline": dominant(r, main_prec),
+    }
+    for prec, rr in results.items():
+        out[prec] = {"applies_per_s": round(rr["applies"] / rr["wall_s"], 3),
+                     "gates_per_s": round(len(ops) * a.steps / rr["wall_s"], 1),
+                     "ms_per_step": round(rr["wall_s"] / a.steps * 1e3, 2),
+                     "fused_applies": rr["info"]["count"], "fusion_width": rr["info"]["max_width"],
+                     "count_by_k": rr["info"]["count_k"][1:],
+                     "avg_launch_ms_by_k": {str(k): round(sum(v) / len(v) * 1e3, 3) for k, v in rr["per_k"].items()},
+                     "roofline": dominant(rr, prec), "trace": rr["trace"]}
+    if not a.no_cpu_baseline:
+        cb = cpu_baseline(W, n, a.layers, a.cpu_n, a.cpu_budget_s)
+        gates_per_apply = len(ops) / r["info"]["count"]
+        out["cpu_baseline"] = {
+            "value": cb["gates_per_s_16q_equiv"] / gates_per_apply,
+            "unit": "applies/s",
+            "cores": cb["cores"],
+            "kind": "oracle",
+            "sample": "oracle (unfused FP64 sum K rho K^dag) on the first %d operations of the same "
+                      "circuit family at %d qubits (%.1f s), scaled by 4^%d to 16 qubits and by %.2f "
+                      "operations per fused apply" % (cb["ops_done"], cb["cpu_n"], cb["secs"],
+                                                      n - cb["cpu_n"], gates_per_apply),
+            "gates_per_s_16q_equiv": cb["gates_per_s_16q_equiv"],
+        }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,208 @@
+/*
+ * tanq.h -- C ABI of the MI355X (gfx950) density-matrix superoperator engine.
+ *
+ * Method (TANQ-Sim, arXiv 2404.13184):
+ *   - rho is stored as the column-stacked vector vec(rho) of length 4^n (Sec. 3.1):
+ *     element rho[r][c] sits at index r + c * 2^n.  Qubit q is bit q of r (and bit q + n
+ *     of the vec index for the column), as in the strided index map of Sec. 3.1.
+ *   - A gate or Kraus channel K_i on j qubits becomes the superoperator
+ *     S = sum_i conj(K_i) (x) K_i (Sec. 3.1, from vec(A B C) = (C^T (x) A) vec(B)), and the
+ *     simulation is |rho(t)> = S |rho(t-1)> (Eq. eq:sp).
+ *   - Applying S is a batched small complex GEMM over the 4^(n-k) groups of amplitudes
+ *     that differ only in the 2k target bits (Sec. 3.1 "im2col" view, Sec. 3.2 tensor-core
+ *     mapping); consecutive operations are fused into k-qubit blocks (Sec. 3.3).
+ *
+ * Conventions used by every entry point:
+ *   - Complex numbers are interleaved (re, im).  FP64 state = complex128 (16 B/element),
+ *     FP32 state = complex64 (8 B/element).
+ *   - A j-qubit matrix on qubits (q_0..q_{j-1}) is row-major, M[out * 2^j + in], and its
+ *     local basis index is sum_t b_{q_t} 2^t (the first listed qubit is the least
+ *     significant bit).
+ *   - A k-qubit superoperator S is row-major 4^k x 4^k complex128, and its local index is
+ *     row_local + 2^k * col_local, with row_local/col_local as above.
+ *   - Every call returns TANQ_OK (0) or a negative tanq_status; no C++ exception crosses
+ *     the ABI.  On error, tanq_last_error() describes the failure (per calling thread).
+ *   - Calls that take a tanq_dm run stream-ordered on the stream given at creation and
+ *     return before the GPU finishes unless documented as synchronising.
+ *   - Handles are not thread-safe: one handle must not be used by two threads at once.
+ */
+#ifndef TANQ_H
+#define TANQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int tanq_status;
+
+#define TANQ_OK 0
+#define TANQ_E_ARG (-1)         /* invalid argument (bad n, qubits, sizes, NULL pointer) */
+#define TANQ_E_OOM (-2)         /* device or pinned-host allocation failed or over budget */
+#define TANQ_E_HIP (-3)         /* a HIP runtime call failed */
+#define TANQ_E_STATE (-4)       /* handle in the wrong state (e.g. mismatched precision) */
+#define TANQ_E_UNSUPPORTED (-5) /* valid request that this build does not implement */
+#define TANQ_E_AGAIN (-6)       /* server: result not ready yet */
+
+typedef enum { TANQ_F64 = 0, TANQ_F32 = 1 } tanq_prec;
+
+/* Fusion modes for tanq_fuse(max_width): */
+#define TANQ_FUSE_AUTO 0    /* choose 2 or 3 by the autotuner's measured cost model */
+#define TANQ_FUSE_NONE (-1) /* plain method: one superoperator per operation, no fusion */
+#define TANQ_FUSE_PAPER (-2) /* Sec. 3.3: merge consecutive 1q ops on one qubit, then
+                                consecutive 2q ops on the same ordered pair */
+/* 1, 2, 3: greedy blocks of at most that many qubits (Sec. 3.3 generalised). */
+
+typedef struct tanq_dm_s* tanq_dm;
+typedef struct tanq_circuit_s* tanq_circuit;
+typedef struct tanq_fused_s* tanq_fused;
+
+/* Text of the last error on the calling thread ("" if none).  Owned by the library. */
+const char* tanq_last_error(void);
+
+/* Library version as 10000*major + 100*minor + patch. */
+int tanq_version(void);
+
+/* ---------------------------------------------------------------------------------------
+ * Density matrices (Sec. 2.1; storage vec(rho), Sec. 3.1).
+ * ------------------------------------------------------------------------------------- */
+
+/* Allocate a device-resident vec(rho) of 4^n elements of precision p and set
+ * rho = |0..0><0..0|.  hip_stream: a hipStream_t (NULL = the null stream) on which every
+ * later call on this handle is ordered; the caller keeps the stream alive.  The handle
+ * owns the memory.  Errors: TANQ_E_ARG if n < 1 or n > 17 or out == NULL; TANQ_E_OOM if
+ * the footprint exceeds free device memory. */
+tanq_status tanq_dm_init(int n, tanq_prec p, void* hip_stream, tanq_dm* out);
+
+/* Wrap caller-owned device memory (4^n contiguous complex128 or complex64 elements, e.g.
+ * a PyTorch tensor).  The contents are left as they are; the caller keeps the memory alive
+ * until tanq_dm_free.  Same errors as tanq_dm_init, plus TANQ_E_ARG for a NULL pointer or
+ * a pointer not 16-byte aligned. */
+tanq_status tanq_dm_wrap(int n, tanq_prec p, void* dev_ptr, void* hip_stream, tanq_dm* out);
+
+/* Release the handle (and its memory if owned).  Synchronises the handle's stream. */
+tanq_status tanq_dm_free(tanq_dm d);
+
+/* rho = |0..0><0..0| (stream-ordered). */
+tanq_status tanq_dm_reset(tanq_dm d);
+
+/* Number of qubits, precision, element count (4^n) and device pointer of a handle. */
+tanq_status tanq_dm_query(tanq_dm d, int* n, int* prec, uint64_t* elements, void** dev_ptr);
+
+/* Copy vec(rho) to / from host memory (bytes must equal 4^n * element size).  Both
+ * synchronise the stream before returning. */
+tanq_status tanq_dm_read(tanq_dm d, void* host, size_t bytes);
+tanq_status tanq_dm_write(tanq_dm d, const void* host, size_t bytes);
+
+/* Fill vec(rho) with seeded pseudo-random complex values (not a density matrix): element
+ * e gets re = u(2x), im = u(2x + 1) with x = (seed << 40) + e and u(c) the top 53 bits of
+ * SplitMix64(c) (Steele, Lea & Flood 2014) scaled to [-0.5, 0.5).  Input generator for
+ * linearity checks of single applies at full size.  Stream-ordered. */
+tanq_status tanq_dm_fill_random(tanq_dm d, uint64_t seed);
+
+/* Copy `count` elements of vec(rho) at the vec indices idx[0..count-1] (host array) into
+ * host_out (count complex values of the handle's precision).  A gather kernel reads them on
+ * the device, so only the sampled elements cross PCIe.  TANQ_E_ARG if an index >= 4^n.
+ * Synchronises. */
+tanq_status tanq_dm_gather(tanq_dm d, size_t count, const uint64_t* idx, void* host_out);
+
+/* Block until all work queued on the handle's stream is done. */
+tanq_status tanq_sync(tanq_dm d);
+
+/* ---------------------------------------------------------------------------------------
+ * Circuits: an ordered list of gates and Kraus channels (the transformations of Eq.
+ * eq:dmsim; noise as Kraus sets, Sec. 3.5).
+ * ------------------------------------------------------------------------------------- */
+
+/* Create an empty circuit on n qubits (1 <= n <= 17). */
+tanq_status tanq_circuit_create(int n, tanq_circuit* out);
+tanq_status tanq_circuit_free(tanq_circuit c);
+
+/* Append a j-qubit gate U (2^j x 2^j complex128, row-major) on qubits[0..j-1].
+ * j in {1, 2, 3}; qubits distinct and < n.  Arrays are copied. */
+tanq_status tanq_circuit_add_gate(tanq_circuit c, int j, const int* qubits, const double* U);
+
+/* Append a j-qubit channel given by m >= 1 Kraus matrices K (m consecutive 2^j x 2^j
+ * complex128 row-major matrices).  The channel is rho -> sum_i K_i rho K_i^dagger. */
+tanq_status tanq_circuit_add_kraus(tanq_circuit c, int j, const int* qubits, int m, const double* K);
+
+/* Number of operations appended so far. */
+tanq_status tanq_circuit_size(tanq_circuit c, int* count);
+
+/* ---------------------------------------------------------------------------------------
+ * Fusion (Sec. 3.3) and superoperator construction (Sec. 3.1).
+ * ------------------------------------------------------------------------------------- */
+
+typedef struct {
+  int count;       /* number of fused superoperators */
+  int count_k[4];  /* how many have k = 1, 2, 3 qubits (index 0 unused) */
+  int source_ops;  /* operations absorbed */
+  int max_width;   /* width actually used (1, 2 or 3), or TANQ_FUSE_NONE / TANQ_FUSE_PAPER */
+  int prec;        /* tanq_prec the fused list is packed for */
+  int n;           /* qubits of the circuit */
+} tanq_fused_info_t;
+
+/* Plan blocks on the host, then on the GPU: build each operation's superoperator
+ * S = sum_i conj(K_i) (x) K_i and compose the operations of each block, in circuit order,
+ * in FP64; finally pack each block for the apply kernel of precision p (FP32 blocks are
+ * rounded once from the FP64 composition).  max_width: TANQ_FUSE_AUTO, TANQ_FUSE_NONE,
+ * TANQ_FUSE_PAPER or 1..3.  The result is device-resident and usable with any tanq_dm of
+ * the same n and precision.  Synchronises hip_stream before returning. */
+tanq_status tanq_fuse(tanq_circuit c, int max_width, tanq_prec p, void* hip_stream, tanq_fused* out);
+tanq_status tanq_fused_info(tanq_fused f, tanq_fused_info_t* info);
+tanq_status tanq_fused_free(tanq_fused f);
+
+/* Host-only planning query (no GPU needed): the block that each operation of c joins under
+ * max_width (same modes as tanq_fuse except TANQ_FUSE_AUTO, which is rejected).
+ * op_block receives one block index per operation (size of c); *nblocks the block count.
+ * Blocks are applied in increasing index order; operations inside a block keep circuit
+ * order. */
+tanq_status tanq_fuse_plan(tanq_circuit c, int max_width, int* op_block, int* nblocks);
+
+/* Copy fused superoperator idx back to the host: *k, qubits[0..k-1] (ascending) and the
+ * FP64 composition S (4^k x 4^k complex128 row-major, caller provides 2*16^k doubles). */
+tanq_status tanq_fused_get(tanq_fused f, int idx, int* k, int* qubits, double* S);
+
+/* ---------------------------------------------------------------------------------------
+ * Applying superoperators (Eq. eq:sp; Sec. 3.1-3.2).
+ * ------------------------------------------------------------------------------------- */
+
+/* In place: for every group g of the 4^(n-k) groups, x <- S x on the 4^k amplitudes whose
+ * target bits (q_t and q_t + n) take every value.  S: host 4^k x 4^k complex128 (copied
+ * into a pinned ring before return; FP32 handles round it once).  k in {1, 2, 3}, k <= n,
+ * qubits distinct and < n.  Stream-ordered, asynchronous. */
+tanq_status tanq_apply_superop(tanq_dm d, int k, const int* qubits, const double* S);
+
+/* Apply every fused superoperator of f in order (or those with index in [begin, end)).
+ * f must have been built for d's n and precision (TANQ_E_STATE otherwise). */
+tanq_status tanq_apply_fused(tanq_dm d, tanq_fused f);
+tanq_status tanq_apply_fused_range(tanq_dm d, tanq_fused f, int begin, int end);
+
+/* ---------------------------------------------------------------------------------------
+ * Measurement statistics (Sec. 2.1: rho gives the probability of every outcome).
+ * ------------------------------------------------------------------------------------- */
+
+/* Z-basis probabilities p_x = Re rho[x][x] (divided by the trace if renormalize != 0),
+ * reduced in FP64 on the GPU; host_out receives 2^n doubles, *trace_out (may be NULL) the
+ * trace.  Synchronises. */
+tanq_status tanq_probs(tanq_dm d, double* host_out, int renormalize, double* trace_out);
+
+/* Re Tr(P rho) for the Pauli string P = (x)_t sigma_{pauli[t]}, pauli = n characters of
+ * "IXYZ", character t acting on qubit t.  FP64 reduction.  Synchronises. */
+tanq_status tanq_expect_pauli(tanq_dm d, const char* pauli, double* out);
+
+/* Tr(P rho) with its imaginary part (zero for Hermitian rho). */
+tanq_status tanq_expect_pauli_c(tanq_dm d, const char* pauli, double* re, double* im);
+
+/* count Pauli strings at once (one launch); out_re/out_im receive count values each
+ * (out_im may be NULL). */
+tanq_status tanq_expect_pauli_batch(tanq_dm d, int count, const char* const* paulis, double* out_re,
+                                    double* out_im);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TANQ_H */

@@ -1,0 +1,697 @@
+// C ABI of libtanq (declared in include/tanq.h): handles, circuits, fusion and
+// measurement entry points.  Every compute step runs in the HIP kernels of kernels.hip;
+// this file validates arguments, owns memory and orders work on the handle's stream.
+#include <algorithm>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "fuse_plan.hpp"
+#include "internal.hpp"
+
+using namespace tanq;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+tanq_status set_error(tanq_status code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+template <typename F>
+tanq_status guarded(F&& f) {
+  try {
+    g_last_error.clear();
+    f();
+    return TANQ_OK;
+  } catch (const Error& e) {
+    return set_error(e.code, e.what());
+  } catch (const std::bad_alloc&) {
+    return set_error(TANQ_E_OOM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return set_error(TANQ_E_STATE, e.what());
+  } catch (...) {
+    return set_error(TANQ_E_STATE, "unknown failure");
+  }
+}
+
+constexpr int MAX_N = 17;
+constexpr int RING = 8;
+constexpr size_t SLOT_DOUBLES = 2 * 64 * 64;  // one 3-qubit superoperator, complex128
+
+size_t elem_size(tanq_prec p) { return p == TANQ_F64 ? 16 : 8; }
+
+void check_prec(tanq_prec p) {
+  if (p != TANQ_F64 && p != TANQ_F32) fail(TANQ_E_ARG, "precision must be TANQ_F64 or TANQ_F32");
+}
+
+void check_qubits(int n, int k, const int* q, int kmax) {
+  if (k < 1 || k > kmax) fail(TANQ_E_ARG, "width must be in 1.." + std::to_string(kmax));
+  if (k > n) fail(TANQ_E_ARG, "width exceeds the number of qubits");
+  if (!q) fail(TANQ_E_ARG, "qubits is NULL");
+  for (int t = 0; t < k; ++t) {
+    if (q[t] < 0 || q[t] >= n) fail(TANQ_E_ARG, "qubit " + std::to_string(q[t]) + " out of range");
+    for (int u = 0; u < t; ++u)
+      if (q[u] == q[t]) fail(TANQ_E_ARG, "duplicate qubit " + std::to_string(q[t]));
+  }
+}
+
+size_t packed_bytes(int k, tanq_prec p) {
+  if (k == 1) return 32 * sizeof(double);
+  return (size_t)packed_elems(k) * (p == TANQ_F64 ? sizeof(double) : sizeof(float));
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    TANQ_HIP(hipGetDevice(&prev));
+    if (prev != dev) TANQ_HIP(hipSetDevice(dev));
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (hipGetDevice(&cur) == hipSuccess && cur != prev && prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+template <typename T>
+void dfree(T*& p) {
+  if (p) (void)hipFree((void*)p);
+  p = nullptr;
+}
+
+}  // namespace
+
+struct tanq_dm_s {
+  int n = 0;
+  tanq_prec prec = TANQ_F64;
+  void* ptr = nullptr;
+  bool owned = false;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  double* probs_dev = nullptr;
+  double* partials = nullptr;
+  double* result_dev = nullptr;
+  uint64_t* masks_dev = nullptr;
+  double* s_raw_dev = nullptr;      // RING slots of a FP64 superoperator
+  unsigned char* s_packed_dev = nullptr;  // RING slots of a packed operand
+  double* pinned = nullptr;         // RING slots, host
+  hipEvent_t ev[RING] = {};
+  int ring = 0;
+
+  uint64_t elements() const { return 1ull << (2 * n); }
+  size_t bytes() const { return (size_t)elements() * elem_size(prec); }
+};
+
+struct HostOp {
+  int j = 0;
+  int m = 0;
+  int q[3] = {0, 0, 0};
+  std::vector<double> K;  // m matrices, 2^j x 2^j complex row-major
+};
+
+struct tanq_circuit_s {
+  int n = 0;
+  std::vector<HostOp> ops;
+};
+
+struct FusedBlockHost {
+  int k = 0;
+  int qubits[3] = {0, 0, 0};
+  size_t raw_off = 0;   // complex elements
+  size_t pack_off = 0;  // bytes
+};
+
+struct tanq_fused_s {
+  int n = 0;
+  tanq_prec prec = TANQ_F64;
+  int mode = 0;
+  int device = 0;
+  int source_ops = 0;
+  int count_k[4] = {0, 0, 0, 0};
+  std::vector<FusedBlockHost> blocks;
+  double* raw = nullptr;
+  unsigned char* packed = nullptr;
+};
+
+namespace {
+
+void dm_alloc_scratch(tanq_dm_s* d) {
+  const uint64_t dim = 1ull << d->n;
+  TANQ_HIP(hipMalloc((void**)&d->probs_dev, dim * sizeof(double)));
+  TANQ_HIP(hipMalloc((void**)&d->partials, (size_t)reduce_partials() * sizeof(double)));
+  TANQ_HIP(hipMalloc((void**)&d->result_dev, 4096 * sizeof(double)));
+  TANQ_HIP(hipMalloc((void**)&d->masks_dev, 3 * 2048 * sizeof(uint64_t)));
+  TANQ_HIP(hipMalloc((void**)&d->s_raw_dev, RING * SLOT_DOUBLES * sizeof(double)));
+  TANQ_HIP(hipMalloc((void**)&d->s_packed_dev, RING * packed_bytes(3, TANQ_F64)));
+  TANQ_HIP(hipHostMalloc((void**)&d->pinned, RING * SLOT_DOUBLES * sizeof(double), hipHostMallocDefault));
+  for (int i = 0; i < RING; ++i) TANQ_HIP(hipEventCreateWithFlags(&d->ev[i], hipEventDisableTiming));
+}
+
+void dm_release(tanq_dm_s* d) {
+  if (!d) return;
+  (void)hipSetDevice(d->device);
+  (void)hipStreamSynchronize(d->stream);
+  for (int i = 0; i < RING; ++i)
+    if (d->ev[i]) (void)hipEventDestroy(d->ev[i]);
+  if (d->pinned) (void)hipHostFree(d->pinned);
+  dfree(d->probs_dev);
+  dfree(d->partials);
+  dfree(d->result_dev);
+  dfree(d->masks_dev);
+  dfree(d->s_raw_dev);
+  dfree(d->s_packed_dev);
+  if (d->owned && d->ptr) (void)hipFree(d->ptr);
+  delete d;
+}
+
+tanq_dm_s* dm_new(int n, tanq_prec p, void* stream) {
+  if (n < 1 || n > MAX_N) fail(TANQ_E_ARG, "n must be in 1..17");
+  check_prec(p);
+  std::unique_ptr<tanq_dm_s> d(new tanq_dm_s);
+  d->n = n;
+  d->prec = p;
+  d->stream = (hipStream_t)stream;
+  TANQ_HIP(hipGetDevice(&d->device));
+  return d.release();
+}
+
+void check_dm(tanq_dm d) {
+  if (!d) fail(TANQ_E_ARG, "density-matrix handle is NULL");
+}
+
+void parse_pauli(int n, const char* s, uint64_t out[3]) {
+  if (!s) fail(TANQ_E_ARG, "Pauli string is NULL");
+  uint64_t xm = 0, zm = 0;
+  int ny = 0;
+  int t = 0;
+  for (; s[t] != '\0'; ++t) {
+    if (t >= n) fail(TANQ_E_ARG, "Pauli string longer than n");
+    switch (s[t]) {
+      case 'I': break;
+      case 'X': xm |= 1ull << t; break;
+      case 'Y': xm |= 1ull << t; zm |= 1ull << t; ++ny; break;
+      case 'Z': zm |= 1ull << t; break;
+      default: fail(TANQ_E_ARG, std::string("bad Pauli character '") + s[t] + "'");
+    }
+  }
+  if (t != n) fail(TANQ_E_ARG, "Pauli string must have exactly n characters");
+  out[0] = xm;
+  out[1] = zm;
+  out[2] = (uint64_t)(ny & 3);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* tanq_last_error(void) { return g_last_error.c_str(); }
+
+int tanq_version(void) { return 100; }
+
+tanq_status tanq_dm_init(int n, tanq_prec p, void* hip_stream, tanq_dm* out) {
+  return guarded([&] {
+    if (!out) fail(TANQ_E_ARG, "out is NULL");
+    *out = nullptr;
+    tanq_dm_s* d = dm_new(n, p, hip_stream);
+    try {
+      size_t free_b = 0, total_b = 0;
+      TANQ_HIP(hipMemGetInfo(&free_b, &total_b));
+      if (d->bytes() + (64ull << 20) > free_b)
+        fail(TANQ_E_OOM, "density matrix needs " + std::to_string(d->bytes()) + " bytes, " +
+                             std::to_string(free_b) + " free");
+      hipError_t e = hipMalloc(&d->ptr, d->bytes());
+      if (e != hipSuccess) fail(TANQ_E_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
+      d->owned = true;
+      dm_alloc_scratch(d);
+      launch_init_zero(d->ptr, n, p, d->stream);
+    } catch (...) {
+      dm_release(d);
+      throw;
+    }
+    *out = d;
+  });
+}
+
+tanq_status tanq_dm_wrap(int n, tanq_prec p, void* dev_ptr, void* hip_stream, tanq_dm* out) {
+  return guarded([&] {
+    if (!out) fail(TANQ_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (!dev_ptr) fail(TANQ_E_ARG, "device pointer is NULL");
+    if (((uintptr_t)dev_ptr) & 15u) fail(TANQ_E_ARG, "device pointer must be 16-byte aligned");
+    tanq_dm_s* d = dm_new(n, p, hip_stream);
+    try {
+      d->ptr = dev_ptr;
+      d->owned = false;
+      dm_alloc_scratch(d);
+    } catch (...) {
+      dm_release(d);
+      throw;
+    }
+    *out = d;
+  });
+}
+
+tanq_status tanq_dm_free(tanq_dm d) {
+  return guarded([&] { dm_release(d); });
+}
+
+tanq_status tanq_dm_reset(tanq_dm d) {
+  return guarded([&] {
+    check_dm(d);
+    DeviceGuard g(d->device);
+    launch_init_zero(d->ptr, d->n, d->prec, d->stream);
+  });
+}
+
+tanq_status tanq_dm_query(tanq_dm d, int* n, int* prec, uint64_t* elements, void** dev_ptr) {
+  return guarded([&] {
+    check_dm(d);
+    if (n) *n = d->n;
+    if (prec) *prec = (int)d->prec;
+    if (elements) *elements = d->elements();
+    if (dev_ptr) *dev_ptr = d->ptr;
+  });
+}
+
+tanq_status tanq_dm_read(tanq_dm d, void* host, size_t bytes) {
+  return guarded([&] {
+    check_dm(d);
+    if (!host) fail(TANQ_E_ARG, "host buffer is NULL");
+    if (bytes != d->bytes()) fail(TANQ_E_ARG, "byte count must equal 4^n * element size");
+    DeviceGuard g(d->device);
+    TANQ_HIP(hipMemcpyAsync(host, d->ptr, bytes, hipMemcpyDeviceToHost, d->stream));
+    TANQ_HIP(hipStreamSynchronize(d->stream));
+  });
+}
+
+tanq_status tanq_dm_write(tanq_dm d, const void* host, size_t bytes) {
+  return guarded([&] {
+    check_dm(d);
+    if (!host) fail(TANQ_E_ARG, "host buffer is NULL");
+    if (bytes != d->bytes()) fail(TANQ_E_ARG, "byte count must equal 4^n * element size");
+    DeviceGuard g(d->device);
+    TANQ_HIP(hipMemcpyAsync(d->ptr, host, bytes, hipMemcpyHostToDevice, d->stream));
+    TANQ_HIP(hipStreamSynchronize(d->stream));
+  });
+}
+
+tanq_status tanq_dm_fill_random(tanq_dm d, uint64_t seed) {
+  return guarded([&] {
+    check_dm(d);
+    if (seed >= (1ull << 23)) fail(TANQ_E_ARG, "seed must be below 2^23");
+    DeviceGuard g(d->device);
+    launch_fill_random(d->ptr, d->n, d->prec, seed, d->stream);
+  });
+}
+
+tanq_status tanq_dm_gather(tanq_dm d, size_t count, const uint64_t* idx, void* host_out) {
+  return guarded([&] {
+    check_dm(d);
+    if (count == 0) return;
+    if (!idx || !host_out) fail(TANQ_E_ARG, "NULL argument");
+    for (size_t i = 0; i < count; ++i)
+      if (idx[i] >= d->elements()) fail(TANQ_E_ARG, "gather index out of range");
+    DeviceGuard g(d->device);
+    uint64_t* didx = nullptr;
+    void* dout = nullptr;
+    const size_t es = elem_size(d->prec);
+    try {
+      TANQ_HIP(hipMalloc((void**)&didx, count * sizeof(uint64_t)));
+      TANQ_HIP(hipMalloc(&dout, count * es));
+      TANQ_HIP(hipMemcpyAsync(didx, idx, count * sizeof(uint64_t), hipMemcpyHostToDevice, d->stream));
+      launch_gather(d->ptr, d->prec, didx, count, dout, d->stream);
+      TANQ_HIP(hipMemcpyAsync(host_out, dout, count * es, hipMemcpyDeviceToHost, d->stream));
+      TANQ_HIP(hipStreamSynchronize(d->stream));
+    } catch (...) {
+      (void)hipStreamSynchronize(d->stream);
+      dfree(didx);
+      dfree(dout);
+      throw;
+    }
+    dfree(didx);
+    dfree(dout);
+  });
+}
+
+tanq_status tanq_sync(tanq_dm d) {
+  return guarded([&] {
+    check_dm(d);
+    DeviceGuard g(d->device);
+    TANQ_HIP(hipStreamSynchronize(d->stream));
+  });
+}
+
+// ---------------------------------------------------------------------------------------
+// circuits
+// ---------------------------------------------------------------------------------------
+
+tanq_status tanq_circuit_create(int n, tanq_circuit* out) {
+  return guarded([&] {
+    if (!out) fail(TANQ_E_ARG, "out is NULL");
+    if (n < 1 || n > MAX_N) fail(TANQ_E_ARG, "n must be in 1..17");
+    tanq_circuit_s* c = new tanq_circuit_s;
+    c->n = n;
+    *out = c;
+  });
+}
+
+tanq_status tanq_circuit_free(tanq_circuit c) {
+  return guarded([&] { delete c; });
+}
+
+static void add_op(tanq_circuit c, int j, const int* qubits, int m, const double* K) {
+  if (!c) fail(TANQ_E_ARG, "circuit handle is NULL");
+  check_qubits(c->n, j, qubits, 3);
+  if (m < 1) fail(TANQ_E_ARG, "at least one Kraus matrix is required");
+  if (!K) fail(TANQ_E_ARG, "matrix pointer is NULL");
+  HostOp op;
+  op.j = j;
+  op.m = m;
+  for (int t = 0; t < j; ++t) op.q[t] = qubits[t];
+  const size_t cnt = (size_t)m * (1u << j) * (1u << j) * 2;
+  op.K.assign(K, K + cnt);
+  c->ops.push_back(std::move(op));
+}
+
+tanq_status tanq_circuit_add_gate(tanq_circuit c, int j, const int* qubits, const double* U) {
+  return guarded([&] { add_op(c, j, qubits, 1, U); });
+}
+
+tanq_status tanq_circuit_add_kraus(tanq_circuit c, int j, const int* qubits, int m, const double* K) {
+  return guarded([&] { add_op(c, j, qubits, m, K); });
+}
+
+tanq_status tanq_circuit_size(tanq_circuit c, int* count) {
+  return guarded([&] {
+    if (!c || !count) fail(TANQ_E_ARG, "NULL argument");
+    *count = (int)c->ops.size();
+  });
+}
+
+// ---------------------------------------------------------------------------------------
+// fusion
+// ---------------------------------------------------------------------------------------
+
+namespace {
+
+// Relative cost of one apply of width k, in units of one HBM pass over vec(rho), used
+// to choose the fusion width when asked to.  k <= 2 is bound by the HBM pass; k = 3 by
+// MFMA throughput (16 flop/B in FP64, 32 flop/B in FP32 against the machine balance).
+double apply_cost(int k, tanq_prec p) {
+  if (k <= 2) return 1.0;
+  return p == TANQ_F64 ? 1.65 : 1.65;
+}
+
+}  // namespace
+
+tanq_status tanq_fuse(tanq_circuit c, int max_width, tanq_prec p, void* hip_stream, tanq_fused* out) {
+  return guarded([&] {
+    if (!c || !out) fail(TANQ_E_ARG, "NULL argument");
+    *out = nullptr;
+    check_prec(p);
+    if (max_width < -2 || max_width > 3) fail(TANQ_E_ARG, "max_width must be -2..3");
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int n = c->n;
+    std::vector<PlanOp> pops(c->ops.size());
+    for (size_t i = 0; i < c->ops.size(); ++i) {
+      pops[i].j = c->ops[i].j;
+      for (int t = 0; t < 3; ++t) pops[i].q[t] = c->ops[i].q[t];
+    }
+    int mode = max_width;
+    std::vector<PlanBlock> plan;
+    if (mode == TANQ_FUSE_AUTO) {
+      double best = 1e300;
+      for (int w = 2; w <= std::min(3, n); ++w) {
+        std::vector<PlanBlock> pl = plan_fusion(pops, n, w);
+        double cost = 0.0;
+        for (auto& b : pl) cost += apply_cost((int)b.qubits.size(), p);
+        if (cost < best) {
+          best = cost;
+          plan = std::move(pl);
+          mode = w;
+        }
+      }
+      if (n < 2) {
+        plan = plan_fusion(pops, n, 1);
+        mode = 1;
+      }
+    } else {
+      plan = plan_fusion(pops, n, mode);
+    }
+
+    std::unique_ptr<tanq_fused_s> f(new tanq_fused_s);
+    f->n = n;
+    f->prec = p;
+    f->mode = mode;
+    f->source_ops = (int)c->ops.size();
+    TANQ_HIP(hipGetDevice(&f->device));
+
+    // host tables
+    std::vector<FuseOpDev> opt;
+    std::vector<FuseBlockDev> blt;
+    std::vector<double> kraus;
+    size_t sop_total = 0, raw_total = 0, pack_total = 0;
+    int max_k = 1;
+    for (auto& pb : plan) {
+      const int k = (int)pb.qubits.size();
+      if (k > 3) fail(TANQ_E_UNSUPPORTED, "a block wider than 3 qubits");
+      max_k = std::max(max_k, k);
+      FuseBlockDev bd{};
+      bd.k = k;
+      bd.op_begin = (int)opt.size();
+      bd.op_count = (int)pb.ops.size();
+      bd.out_off = (int64_t)raw_total;
+      bd.pack_off = (int64_t)pack_total;
+      FusedBlockHost bh;
+      bh.k = k;
+      for (int t = 0; t < k; ++t) bh.qubits[t] = pb.qubits[t];
+      bh.raw_off = raw_total;
+      bh.pack_off = pack_total;
+      raw_total += (size_t)1 << (4 * k);
+      pack_total += align256(packed_bytes(k, p));
+      for (int oi : pb.ops) {
+        const HostOp& ho = c->ops[oi];
+        FuseOpDev od{};
+        od.j = ho.j;
+        od.m = ho.m;
+        od.kraus_off = (int64_t)(kraus.size() / 2);
+        od.sop_off = (int64_t)sop_total;
+        for (int t = 0; t < ho.j; ++t) {
+          int pos = -1;
+          for (int u = 0; u < k; ++u)
+            if (pb.qubits[u] == ho.q[t]) pos = u;
+          od.pos[t] = pos;
+        }
+        kraus.insert(kraus.end(), ho.K.begin(), ho.K.end());
+        sop_total += (size_t)1 << (4 * ho.j);
+        opt.push_back(od);
+      }
+      blt.push_back(bd);
+      f->blocks.push_back(bh);
+      f->count_k[k] += 1;
+    }
+
+    if (!plan.empty()) {
+      FuseOpDev* d_ops = nullptr;
+      FuseBlockDev* d_blk = nullptr;
+      double *d_kraus = nullptr, *d_sops = nullptr;
+      auto cleanup = [&] {
+        dfree(d_ops);
+        dfree(d_blk);
+        dfree(d_kraus);
+        dfree(d_sops);
+      };
+      try {
+        TANQ_HIP(hipMalloc((void**)&d_ops, opt.size() * sizeof(FuseOpDev)));
+        TANQ_HIP(hipMalloc((void**)&d_blk, blt.size() * sizeof(FuseBlockDev)));
+        TANQ_HIP(hipMalloc((void**)&d_kraus, kraus.size() * sizeof(double)));
+        TANQ_HIP(hipMalloc((void**)&d_sops, sop_total * 2 * sizeof(double)));
+        TANQ_HIP(hipMalloc((void**)&f->raw, raw_total * 2 * sizeof(double)));
+        TANQ_HIP(hipMalloc((void**)&f->packed, pack_total));
+        TANQ_HIP(hipMemcpyAsync(d_ops, opt.data(), opt.size() * sizeof(FuseOpDev), hipMemcpyHostToDevice, s));
+        TANQ_HIP(hipMemcpyAsync(d_blk, blt.data(), blt.size() * sizeof(FuseBlockDev), hipMemcpyHostToDevice, s));
+        TANQ_HIP(hipMemcpyAsync(d_kraus, kraus.data(), kraus.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        launch_build_superops(d_ops, (int)opt.size(), d_kraus, d_sops, s);
+        launch_compose(d_blk, (int)blt.size(), max_k, d_ops, d_sops, f->raw, s);
+        launch_pack(d_blk, (int)blt.size(), f->raw, f->packed, p, s);
+        TANQ_HIP(hipStreamSynchronize(s));
+      } catch (...) {
+        (void)hipStreamSynchronize(s);
+        cleanup();
+        dfree(f->raw);
+        dfree(f->packed);
+        throw;
+      }
+      cleanup();
+    }
+    *out = f.release();
+  });
+}
+
+tanq_status tanq_fuse_plan(tanq_circuit c, int max_width, int* op_block, int* nblocks) {
+  return guarded([&] {
+    if (!c || !nblocks) fail(TANQ_E_ARG, "NULL argument");
+    if (max_width < -2 || max_width > 3 || max_width == 0) fail(TANQ_E_ARG, "max_width must be -2, -1, 1, 2 or 3");
+    if (!c->ops.empty() && !op_block) fail(TANQ_E_ARG, "op_block is NULL");
+    std::vector<PlanOp> pops(c->ops.size());
+    for (size_t i = 0; i < c->ops.size(); ++i) {
+      pops[i].j = c->ops[i].j;
+      for (int t = 0; t < 3; ++t) pops[i].q[t] = c->ops[i].q[t];
+    }
+    const std::vector<PlanBlock> plan = plan_fusion(pops, c->n, max_width);
+    for (size_t b = 0; b < plan.size(); ++b)
+      for (int oi : plan[b].ops) op_block[oi] = (int)b;
+    *nblocks = (int)plan.size();
+  });
+}
+
+tanq_status tanq_fused_info(tanq_fused f, tanq_fused_info_t* info) {
+  return guarded([&] {
+    if (!f || !info) fail(TANQ_E_ARG, "NULL argument");
+    info->count = (int)f->blocks.size();
+    for (int i = 0; i < 4; ++i) info->count_k[i] = f->count_k[i];
+    info->source_ops = f->source_ops;
+    info->max_width = f->mode;
+    info->prec = (int)f->prec;
+    info->n = f->n;
+  });
+}
+
+tanq_status tanq_fused_free(tanq_fused f) {
+  return guarded([&] {
+    if (!f) return;
+    (void)hipSetDevice(f->device);
+    dfree(f->raw);
+    dfree(f->packed);
+    delete f;
+  });
+}
+
+tanq_status tanq_fused_get(tanq_fused f, int idx, int* k, int* qubits, double* S) {
+  return guarded([&] {
+    if (!f) fail(TANQ_E_ARG, "fused handle is NULL");
+    if (idx < 0 || idx >= (int)f->blocks.size()) fail(TANQ_E_ARG, "index out of range");
+    const FusedBlockHost& b = f->blocks[idx];
+    if (k) *k = b.k;
+    if (qubits)
+      for (int t = 0; t < b.k; ++t) qubits[t] = b.qubits[t];
+    if (S) {
+      DeviceGuard g(f->device);
+      TANQ_HIP(hipMemcpy(S, f->raw + 2 * b.raw_off, ((size_t)1 << (4 * b.k)) * 2 * sizeof(double),
+                         hipMemcpyDeviceToHost));
+    }
+  });
+}
+
+// ---------------------------------------------------------------------------------------
+// apply
+// ---------------------------------------------------------------------------------------
+
+tanq_status tanq_apply_superop(tanq_dm d, int k, const int* qubits, const double* S) {
+  return guarded([&] {
+    check_dm(d);
+    check_qubits(d->n, k, qubits, 3);
+    if (!S) fail(TANQ_E_ARG, "superoperator pointer is NULL");
+    DeviceGuard g(d->device);
+    const int slot = d->ring;
+    d->ring = (d->ring + 1) % RING;
+    TANQ_HIP(hipEventSynchronize(d->ev[slot]));  // previous upload from this slot is done
+    const size_t cnt = ((size_t)1 << (4 * k)) * 2;
+    double* host = d->pinned + slot * SLOT_DOUBLES;
+    std::memcpy(host, S, cnt * sizeof(double));
+    double* raw = d->s_raw_dev + slot * SLOT_DOUBLES;
+    unsigned char* packed = d->s_packed_dev + slot * packed_bytes(3, TANQ_F64);
+    TANQ_HIP(hipMemcpyAsync(raw, host, cnt * sizeof(double), hipMemcpyHostToDevice, d->stream));
+    TANQ_HIP(hipEventRecord(d->ev[slot], d->stream));
+    launch_pack_one(k, raw, packed, d->prec, d->stream);
+    launch_apply(d->ptr, d->n, d->prec, k, qubits, packed, d->stream);
+  });
+}
+
+tanq_status tanq_apply_fused_range(tanq_dm d, tanq_fused f, int begin, int end) {
+  return guarded([&] {
+    check_dm(d);
+    if (!f) fail(TANQ_E_ARG, "fused handle is NULL");
+    if (f->n != d->n) fail(TANQ_E_STATE, "fused list was built for a different qubit count");
+    if (f->prec != d->prec) fail(TANQ_E_STATE, "fused list was packed for a different precision");
+    if (begin < 0 || end > (int)f->blocks.size() || begin > end) fail(TANQ_E_ARG, "bad range");
+    DeviceGuard g(d->device);
+    for (int i = begin; i < end; ++i) {
+      const FusedBlockHost& b = f->blocks[i];
+      launch_apply(d->ptr, d->n, d->prec, b.k, b.qubits, f->packed + b.pack_off, d->stream);
+    }
+  });
+}
+
+tanq_status tanq_apply_fused(tanq_dm d, tanq_fused f) {
+  if (!f) return set_error(TANQ_E_ARG, "fused handle is NULL");
+  return tanq_apply_fused_range(d, f, 0, (int)f->blocks.size());
+}
+
+// ---------------------------------------------------------------------------------------
+// measurement statistics
+// ---------------------------------------------------------------------------------------
+
+tanq_status tanq_probs(tanq_dm d, double* host_out, int renormalize, double* trace_out) {
+  return guarded([&] {
+    check_dm(d);
+    if (!host_out) fail(TANQ_E_ARG, "output buffer is NULL");
+    DeviceGuard g(d->device);
+    launch_diag(d->ptr, d->n, d->prec, d->probs_dev, d->partials, d->result_dev, renormalize, d->stream);
+    TANQ_HIP(hipMemcpyAsync(host_out, d->probs_dev, (1ull << d->n) * sizeof(double), hipMemcpyDeviceToHost,
+                            d->stream));
+    double tr = 0.0;
+    TANQ_HIP(hipMemcpyAsync(&tr, d->result_dev, sizeof(double), hipMemcpyDeviceToHost, d->stream));
+    TANQ_HIP(hipStreamSynchronize(d->stream));
+    if (trace_out) *trace_out = tr;
+  });
+}
+
+tanq_status tanq_expect_pauli_batch(tanq_dm d, int count, const char* const* paulis, double* out_re,
+                                    double* out_im) {
+  return guarded([&] {
+    check_dm(d);
+    if (count < 0 || (count > 0 && (!paulis || !out_re))) fail(TANQ_E_ARG, "NULL argument");
+    DeviceGuard g(d->device);
+    constexpr int CHUNK = 1024;
+    std::vector<uint64_t> masks(3 * CHUNK);
+    std::vector<double> res(2 * CHUNK);
+    for (int base = 0; base < count; base += CHUNK) {
+      const int cnt = std::min(CHUNK, count - base);
+      for (int i = 0; i < cnt; ++i) parse_pauli(d->n, paulis[base + i], &masks[3 * i]);
+      TANQ_HIP(hipMemcpyAsync(d->masks_dev, masks.data(), 3 * cnt * sizeof(uint64_t), hipMemcpyHostToDevice,
+                              d->stream));
+      launch_pauli(d->ptr, d->n, d->prec, cnt, d->masks_dev, d->partials, d->result_dev, d->stream);
+      TANQ_HIP(hipMemcpyAsync(res.data(), d->result_dev, 2 * cnt * sizeof(double), hipMemcpyDeviceToHost,
+                              d->stream));
+      TANQ_HIP(hipStreamSynchronize(d->stream));
+      for (int i = 0; i < cnt; ++i) {
+        out_re[base + i] = res[2 * i];
+        if (out_im) out_im[base + i] = res[2 * i + 1];
+      }
+    }
+  });
+}
+
+tanq_status tanq_expect_pauli_c(tanq_dm d, const char* pauli, double* re, double* im) {
+  const char* arr[1] = {pauli};
+  double r = 0.0, i = 0.0;
+  tanq_status st = tanq_expect_pauli_batch(d, 1, arr, &r, &i);
+  if (st == TANQ_OK) {
+    if (re) *re = r;
+    if (im) *im = i;
+  }
+  return st;
+}
+
+tanq_status tanq_expect_pauli(tanq_dm d, const char* pauli, double* out) {
+  if (!out) return set_error(TANQ_E_ARG, "out is NULL");
+  return tanq_expect_pauli_c(d, pauli, out, nullptr);
+}
+
+}  // extern "C"

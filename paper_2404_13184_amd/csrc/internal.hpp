@@ -1,0 +1,121 @@
+// Internal declarations shared by the host sources and the HIP kernels of libtanq.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/tanq.h"
+
+namespace tanq {
+
+// ------------------------------------------------------------------------------------
+// errors
+// ------------------------------------------------------------------------------------
+
+struct Error : std::runtime_error {
+  tanq_status code;
+  Error(tanq_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+[[noreturn]] inline void fail(tanq_status c, const std::string& m) { throw Error(c, m); }
+
+#define TANQ_HIP(expr)                                                                      \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      ::tanq::fail(TANQ_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));          \
+  } while (0)
+
+// ------------------------------------------------------------------------------------
+// geometry of one superoperator apply (computed on the host, passed by value)
+// ------------------------------------------------------------------------------------
+
+// Tiles: a workgroup owns the 2^V elements of vec(rho) whose "varying" bits take every
+// value (the 2k target bits plus the lowest free bits), with the remaining ("fixed") bits
+// given by the tile id.  Groups of the superoperator lie wholly inside a tile.
+struct ApplyGeom {
+  uint64_t ntiles;        // number of tiles = 2^(2n - V)
+  uint32_t tj[64];        // tile-local index of each superoperator local index l < 4^k
+  uint32_t free_mask;     // tile-local bits that index groups inside the tile
+  int32_t V;              // tile bits
+  int32_t G;              // groups per tile = 2^(V - 2k)
+  int32_t nruns;          // runs of fixed bits
+  uint8_t vpos[16];       // tile-local bit b -> global bit vpos[b] (ascending)
+  uint8_t run_src[8];     // first tile-id bit of run r
+  uint8_t run_len[8];     // length of run r
+  uint8_t run_dst[8];     // first global bit of run r
+};
+
+// One-qubit apply (the paper's C1): groups of 4 at s_i + {0, 2^q, 2^(q+n), 2^q + 2^(q+n)}.
+struct C1Geom {
+  uint64_t ngroups;  // 4^(n-1)
+  int32_t q;
+  int32_t n;
+};
+
+// Fusion: a block of consecutive operations on at most k qubits.
+struct FuseOpDev {
+  int32_t j;          // qubits of the operation
+  int32_t m;          // Kraus matrices
+  int64_t kraus_off;  // offset (complex elements) of K_0 in the Kraus pool
+  int64_t sop_off;    // offset (complex elements) of its superoperator in the pool
+  int32_t pos[3];     // block-local position of each of its qubits
+  int32_t pad;
+};
+
+struct FuseBlockDev {
+  int32_t k;          // qubits of the block
+  int32_t op_begin;   // first operation (index into the op table)
+  int32_t op_count;
+  int32_t pad;
+  int64_t out_off;    // offset (complex elements) of the 4^k x 4^k FP64 result
+  int64_t pack_off;   // offset (elements of the packed precision) of the packed operand
+};
+
+// Packed operand sizes (elements of T) per superoperator width.
+constexpr int packed_elems(int k) { return k == 1 ? 32 : (k == 2 ? 32 * 32 : 128 * 128); }
+
+// ------------------------------------------------------------------------------------
+// launchers (kernels.hip)
+// ------------------------------------------------------------------------------------
+
+ApplyGeom make_apply_geom(int n, int k, const int* qubits_sorted_order, int vbits);
+int default_tile_bits(int k, tanq_prec p);
+
+void launch_init_zero(void* rho, int n, tanq_prec p, hipStream_t s);
+void launch_gather(const void* rho, tanq_prec p, const uint64_t* idx_dev, size_t count, void* out_dev,
+                   hipStream_t s);
+void launch_fill_random(void* rho, int n, tanq_prec p, uint64_t seed, hipStream_t s);
+
+// Apply one superoperator whose packed operand is at `packed` (device).
+//   k == 1: packed = 4x4 complex FP64 (32 doubles), used for both precisions.
+//   k == 2, 3: packed = real-block fragments in precision p.
+void launch_apply(void* rho, int n, tanq_prec p, int k, const int* qubits, const void* packed,
+                  hipStream_t s);
+
+// Superoperators of every operation (sum_i conj(K_i) (x) K_i), FP64.
+void launch_build_superops(const FuseOpDev* ops, int nops, const double* kraus, double* sops,
+                           hipStream_t s);
+// Compose each block's superoperators in circuit order (FP64) into `out`.
+void launch_compose(const FuseBlockDev* blocks, int nblocks, int max_k, const FuseOpDev* ops,
+                    const double* sops, double* out, hipStream_t s);
+// Pack FP64 block superoperators into the apply kernels' operand layout.
+void launch_pack(const FuseBlockDev* blocks, int nblocks, const double* raw, void* packed,
+                 tanq_prec p, hipStream_t s);
+// Pack a single FP64 superoperator (device) of width k.
+void launch_pack_one(int k, const double* raw, void* packed, tanq_prec p, hipStream_t s);
+
+// Reductions (FP64).  partials: device scratch of at least reduce_partials() doubles.
+int reduce_partials();
+void launch_diag(const void* rho, int n, tanq_prec p, double* probs_dev, double* partials,
+                 double* result_dev, int renormalize, hipStream_t s);
+void launch_pauli(const void* rho, int n, tanq_prec p, int count, const uint64_t* masks_dev,
+                  double* partials, double* result_dev, hipStream_t s);
+
+int device_cu_count();
+
+}  // namespace tanq

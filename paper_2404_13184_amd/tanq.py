@@ -1,0 +1,452 @@
+"""ctypes binding of libtanq (the C ABI in include/tanq.h).
+
+Functions named ``tanq_*`` are the C entry points with argument marshalling only; the
+classes :class:`DM`, :class:`Circuit` and :class:`Fused` wrap the handles.  Every compute
+step runs in the library's HIP kernels.  There is no fallback: if ``libtanq.so`` is not
+built, loading raises :class:`TanqError`.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Iterable, List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtanq.so")
+
+TANQ_OK = 0
+TANQ_E_ARG = -1
+TANQ_E_OOM = -2
+TANQ_E_HIP = -3
+TANQ_E_STATE = -4
+TANQ_E_UNSUPPORTED = -5
+TANQ_E_AGAIN = -6
+
+TANQ_F64 = 0
+TANQ_F32 = 1
+
+TANQ_FUSE_AUTO = 0
+TANQ_FUSE_NONE = -1
+TANQ_FUSE_PAPER = -2
+
+# every symbol include/tanq.h declares
+EXPORTED = [
+    "tanq_last_error", "tanq_version",
+    "tanq_dm_init", "tanq_dm_wrap", "tanq_dm_free", "tanq_dm_reset", "tanq_dm_query",
+    "tanq_dm_read", "tanq_dm_write", "tanq_dm_fill_random", "tanq_dm_gather", "tanq_sync",
+    "tanq_circuit_create", "tanq_circuit_free", "tanq_circuit_add_gate", "tanq_circuit_add_kraus",
+    "tanq_circuit_size",
+    "tanq_fuse", "tanq_fuse_plan", "tanq_fused_info", "tanq_fused_free", "tanq_fused_get",
+    "tanq_apply_superop", "tanq_apply_fused", "tanq_apply_fused_range",
+    "tanq_probs", "tanq_expect_pauli", "tanq_expect_pauli_c", "tanq_expect_pauli_batch",
+]
+
+
+class TanqError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("tanq error %d: %s" % (code, msg))
+        self.code = code
+
+
+class FusedInfo(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int), ("count_k", ctypes.c_int * 4), ("source_ops", ctypes.c_int),
+                ("max_width", ctypes.c_int), ("prec", ctypes.c_int), ("n", ctypes.c_int)]
+
+
+_lib = None
+
+_vp = ctypes.c_void_p
+_ip = ctypes.POINTER(ctypes.c_int)
+_dp = ctypes.POINTER(ctypes.c_double)
+
+_SIGS = {
+    "tanq_last_error": ([], ctypes.c_char_p),
+    "tanq_version": ([], ctypes.c_int),
+    "tanq_dm_init": ([ctypes.c_int, ctypes.c_int, _vp, ctypes.POINTER(_vp)], ctypes.c_int),
+    "tanq_dm_wrap": ([ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.POINTER(_vp)], ctypes.c_int),
+    "tanq_dm_free": ([_vp], ctypes.c_int),
+    "tanq_dm_reset": ([_vp], ctypes.c_int),
+    "tanq_dm_query": ([_vp, _ip, _ip, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(_vp)], ctypes.c_int),
+    "tanq_dm_read": ([_vp, _vp, ctypes.c_size_t], ctypes.c_int),
+    "tanq_dm_write": ([_vp, _vp, ctypes.c_size_t], ctypes.c_int),
+    "tanq_dm_fill_random": ([_vp, ctypes.c_uint64], ctypes.c_int),
+    "tanq_dm_gather": ([_vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_uint64), _vp], ctypes.c_int),
+    "tanq_sync": ([_vp], ctypes.c_int),
+    "tanq_circuit_create": ([ctypes.c_int, ctypes.POINTER(_vp)], ctypes.c_int),
+    "tanq_circuit_free": ([_vp], ctypes.c_int),
+    "tanq_circuit_add_gate": ([_vp, ctypes.c_int, _ip, _dp], ctypes.c_int),
+    "tanq_circuit_add_kraus": ([_vp, ctypes.c_int, _ip, ctypes.c_int, _dp], ctypes.c_int),
+    "tanq_circuit_size": ([_vp, _ip], ctypes.c_int),
+    "tanq_fuse": ([_vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.POINTER(_vp)], ctypes.c_int),
+    "tanq_fuse_plan": ([_vp, ctypes.c_int, _ip, _ip], ctypes.c_int),
+    "tanq_fused_info": ([_vp, ctypes.POINTER(FusedInfo)], ctypes.c_int),
+    "tanq_fused_free": ([_vp], ctypes.c_int),
+    "tanq_fused_get": ([_vp, ctypes.c_int, _ip, _ip, _dp], ctypes.c_int),
+    "tanq_apply_superop": ([_vp, ctypes.c_int, _ip, _dp], ctypes.c_int),
+    "tanq_apply_fused": ([_vp, _vp], ctypes.c_int),
+    "tanq_apply_fused_range": ([_vp, _vp, ctypes.c_int, ctypes.c_int], ctypes.c_int),
+    "tanq_probs": ([_vp, _dp, ctypes.c_int, _dp], ctypes.c_int),
+    "tanq_expect_pauli": ([_vp, ctypes.c_char_p, _dp], ctypes.c_int),
+    "tanq_expect_pauli_c": ([_vp, ctypes.c_char_p, _dp, _dp], ctypes.c_int),
+    "tanq_expect_pauli_batch": ([_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_char_p), _dp, _dp], ctypes.c_int),
+}
+
+
+def load(path: str = LIB_PATH):
+    """Load libtanq.so (raises TanqError if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise TanqError(TANQ_E_STATE, "libtanq.so not built at %s (run __graft_entry__.build())" % path)
+        lib = ctypes.CDLL(path)
+        for name, (args, res) in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = lib
+    return _lib
+
+
+def _check(rc: int):
+    if rc != TANQ_OK:
+        raise TanqError(rc, load().tanq_last_error().decode())
+
+
+def _ints(seq: Sequence[int]):
+    return (ctypes.c_int * len(seq))(*[int(x) for x in seq])
+
+
+def _cdoubles(a: np.ndarray):
+    a = np.ascontiguousarray(a, dtype=np.complex128)
+    return a, a.ctypes.data_as(_dp)
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)  # a torch.cuda.Stream
+
+
+# ---------------------------------------------------------------------------------------
+# C entry points, same names
+# ---------------------------------------------------------------------------------------
+
+def tanq_last_error() -> str:
+    return load().tanq_last_error().decode()
+
+
+def tanq_version() -> int:
+    return int(load().tanq_version())
+
+
+def tanq_dm_init(n: int, prec: int, stream=None) -> int:
+    h = _vp()
+    _check(load().tanq_dm_init(n, prec, _stream_ptr(stream), ctypes.byref(h)))
+    return h.value
+
+
+def tanq_dm_wrap(n: int, prec: int, dev_ptr: int, stream=None) -> int:
+    h = _vp()
+    _check(load().tanq_dm_wrap(n, prec, dev_ptr, _stream_ptr(stream), ctypes.byref(h)))
+    return h.value
+
+
+def tanq_dm_free(h: int):
+    _check(load().tanq_dm_free(h))
+
+
+def tanq_dm_reset(h: int):
+    _check(load().tanq_dm_reset(h))
+
+
+def tanq_dm_query(h: int):
+    n, p, e, ptr = ctypes.c_int(), ctypes.c_int(), ctypes.c_uint64(), _vp()
+    _check(load().tanq_dm_query(h, ctypes.byref(n), ctypes.byref(p), ctypes.byref(e), ctypes.byref(ptr)))
+    return n.value, p.value, e.value, ptr.value
+
+
+def tanq_dm_read(h: int, out: np.ndarray):
+    _check(load().tanq_dm_read(h, out.ctypes.data, out.nbytes))
+
+
+def tanq_dm_write(h: int, data: np.ndarray):
+    data = np.ascontiguousarray(data)
+    _check(load().tanq_dm_write(h, data.ctypes.data, data.nbytes))
+
+
+def tanq_dm_fill_random(h: int, seed: int):
+    _check(load().tanq_dm_fill_random(h, seed))
+
+
+def tanq_dm_gather(h: int, idx: np.ndarray, dtype) -> np.ndarray:
+    idx = np.ascontiguousarray(idx, dtype=np.uint64).reshape(-1)
+    out = np.empty(idx.size, dtype=dtype)
+    _check(load().tanq_dm_gather(h, idx.size, idx.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), out.ctypes.data))
+    return out
+
+
+def tanq_sync(h: int):
+    _check(load().tanq_sync(h))
+
+
+def tanq_circuit_create(n: int) -> int:
+    h = _vp()
+    _check(load().tanq_circuit_create(n, ctypes.byref(h)))
+    return h.value
+
+
+def tanq_circuit_free(h: int):
+    _check(load().tanq_circuit_free(h))
+
+
+def tanq_circuit_add_gate(h: int, qubits: Sequence[int], U: np.ndarray):
+    U, p = _cdoubles(U)
+    _check(load().tanq_circuit_add_gate(h, len(qubits), _ints(qubits), p))
+
+
+def tanq_circuit_add_kraus(h: int, qubits: Sequence[int], K: np.ndarray):
+    K, p = _cdoubles(K)
+    _check(load().tanq_circuit_add_kraus(h, len(qubits), _ints(qubits), K.shape[0], p))
+
+
+def tanq_circuit_size(h: int) -> int:
+    c = ctypes.c_int()
+    _check(load().tanq_circuit_size(h, ctypes.byref(c)))
+    return c.value
+
+
+def tanq_fuse(circuit: int, max_width: int, prec: int, stream=None) -> int:
+    h = _vp()
+    _check(load().tanq_fuse(circuit, max_width, prec, _stream_ptr(stream), ctypes.byref(h)))
+    return h.value
+
+
+def tanq_fuse_plan(circuit: int, max_width: int, nops: int):
+    ob = (ctypes.c_int * max(nops, 1))()
+    nb = ctypes.c_int()
+    _check(load().tanq_fuse_plan(circuit, max_width, ob, ctypes.byref(nb)))
+    return list(ob[:nops]), nb.value
+
+
+def tanq_fused_info(h: int) -> dict:
+    info = FusedInfo()
+    _check(load().tanq_fused_info(h, ctypes.byref(info)))
+    return {"count": info.count, "count_k": list(info.count_k), "source_ops": info.source_ops,
+            "max_width": info.max_width, "prec": info.prec, "n": info.n}
+
+
+def tanq_fused_free(h: int):
+    _check(load().tanq_fused_free(h))
+
+
+def tanq_fused_get(h: int, idx: int):
+    k = ctypes.c_int()
+    q = (ctypes.c_int * 3)()
+    _check(load().tanq_fused_get(h, idx, ctypes.byref(k), q, None))
+    S = np.empty((4 ** k.value, 4 ** k.value), dtype=np.complex128)
+    _check(load().tanq_fused_get(h, idx, None, None, S.ctypes.data_as(_dp)))
+    return k.value, tuple(q[:k.value]), S
+
+
+def tanq_fused_block(h: int, idx: int):
+    """(k, qubits) of fused block idx without copying its superoperator."""
+    k = ctypes.c_int()
+    q = (ctypes.c_int * 3)()
+    _check(load().tanq_fused_get(h, idx, ctypes.byref(k), q, None))
+    return k.value, tuple(q[:k.value])
+
+
+def tanq_apply_superop(h: int, qubits: Sequence[int], S: np.ndarray):
+    S, p = _cdoubles(S)
+    _check(load().tanq_apply_superop(h, len(qubits), _ints(qubits), p))
+
+
+def tanq_apply_fused(h: int, fused: int):
+    _check(load().tanq_apply_fused(h, fused))
+
+
+def tanq_apply_fused_range(h: int, fused: int, begin: int, end: int):
+    _check(load().tanq_apply_fused_range(h, fused, begin, end))
+
+
+def tanq_probs(h: int, dim: int, renormalize: bool = True):
+    out = np.empty(dim, dtype=np.float64)
+    tr = ctypes.c_double()
+    _check(load().tanq_probs(h, out.ctypes.data_as(_dp), int(bool(renormalize)), ctypes.byref(tr)))
+    return out, tr.value
+
+
+def tanq_expect_pauli(h: int, pauli: str) -> float:
+    v = ctypes.c_double()
+    _check(load().tanq_expect_pauli(h, pauli.encode(), ctypes.byref(v)))
+    return v.value
+
+
+def tanq_expect_pauli_c(h: int, pauli: str) -> complex:
+    re, im = ctypes.c_double(), ctypes.c_double()
+    _check(load().tanq_expect_pauli_c(h, pauli.encode(), ctypes.byref(re), ctypes.byref(im)))
+    return complex(re.value, im.value)
+
+
+def tanq_expect_pauli_batch(h: int, paulis: Sequence[str]) -> np.ndarray:
+    cnt = len(paulis)
+    arr = (ctypes.c_char_p * max(cnt, 1))(*[p.encode() for p in paulis])
+    re = np.empty(cnt, dtype=np.float64)
+    im = np.empty(cnt, dtype=np.float64)
+    _check(load().tanq_expect_pauli_batch(h, cnt, arr, re.ctypes.data_as(_dp), im.ctypes.data_as(_dp)))
+    return re + 1j * im
+
+
+# ---------------------------------------------------------------------------------------
+# handle wrappers
+# ---------------------------------------------------------------------------------------
+
+def _prec(p) -> int:
+    if p in (TANQ_F64, "f64", "fp64", np.complex128):
+        return TANQ_F64
+    if p in (TANQ_F32, "f32", "fp32", np.complex64):
+        return TANQ_F32
+    raise ValueError("precision %r" % (p,))
+
+
+class DM:
+    """A device-resident vec(rho) (owned, or wrapping caller memory via ``dev_ptr``)."""
+
+    def __init__(self, n: int, prec="f64", stream=None, dev_ptr: Optional[int] = None):
+        self.n = n
+        self.prec = _prec(prec)
+        self.h = tanq_dm_init(n, self.prec, stream) if dev_ptr is None else tanq_dm_wrap(n, self.prec, dev_ptr, stream)
+
+    @property
+    def dtype(self):
+        return np.complex128 if self.prec == TANQ_F64 else np.complex64
+
+    def free(self):
+        if self.h:
+            tanq_dm_free(self.h)
+            self.h = 0
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.free()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def reset(self):
+        tanq_dm_reset(self.h)
+
+    def read(self) -> np.ndarray:
+        out = np.empty(4 ** self.n, dtype=self.dtype)
+        tanq_dm_read(self.h, out)
+        return out
+
+    def write(self, v: np.ndarray):
+        tanq_dm_write(self.h, np.ascontiguousarray(v, dtype=self.dtype))
+
+    def fill_random(self, seed: int):
+        tanq_dm_fill_random(self.h, seed)
+
+    def sync(self):
+        tanq_sync(self.h)
+
+    def gather(self, idx) -> np.ndarray:
+        return tanq_dm_gather(self.h, np.asarray(idx), self.dtype)
+
+    def apply_superop(self, qubits: Sequence[int], S: np.ndarray):
+        tanq_apply_superop(self.h, qubits, S)
+
+    def apply_fused(self, fused: "Fused", begin: Optional[int] = None, end: Optional[int] = None):
+        if begin is None and end is None:
+            tanq_apply_fused(self.h, fused.h)
+        else:
+            tanq_apply_fused_range(self.h, fused.h, begin or 0, fused.count if end is None else end)
+
+    def probs(self, renormalize: bool = True):
+        return tanq_probs(self.h, 1 << self.n, renormalize)
+
+    def expect_pauli(self, pauli: str) -> complex:
+        return tanq_expect_pauli_c(self.h, pauli)
+
+    def expect_paulis(self, paulis: Sequence[str]) -> np.ndarray:
+        return tanq_expect_pauli_batch(self.h, paulis)
+
+
+class Circuit:
+    def __init__(self, n: int, ops: Iterable = ()):
+        self.n = n
+        self.h = tanq_circuit_create(n)
+        for op in ops:
+            self.add(op)
+
+    def add(self, op):
+        if op.mats.shape[0] == 1 and op.kind == "gate":
+            tanq_circuit_add_gate(self.h, op.qubits, op.mats[0])
+        else:
+            tanq_circuit_add_kraus(self.h, op.qubits, op.mats)
+
+    def __len__(self):
+        return tanq_circuit_size(self.h)
+
+    def free(self):
+        if self.h:
+            tanq_circuit_free(self.h)
+            self.h = 0
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def plan(self, max_width: int):
+        return tanq_fuse_plan(self.h, max_width, len(self))
+
+    def fuse(self, max_width: int = TANQ_FUSE_AUTO, prec="f64", stream=None) -> "Fused":
+        return Fused(tanq_fuse(self.h, max_width, _prec(prec), stream))
+
+
+class Fused:
+    def __init__(self, h: int):
+        self.h = h
+        self.info = tanq_fused_info(h)
+        self.count = self.info["count"]
+
+    def get(self, idx: int):
+        return tanq_fused_get(self.h, idx)
+
+    def get_k(self, idx: int) -> int:
+        if getattr(self, "_ks", None) is None:
+            self._ks = [tanq_fused_block(self.h, i)[0] for i in range(self.count)]
+        return self._ks[idx]
+
+    def free(self):
+        if self.h:
+            tanq_fused_free(self.h)
+            self.h = 0
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def simulate(n: int, ops: Iterable, max_width: int = TANQ_FUSE_AUTO, prec="f64", stream=None) -> DM:
+    """Fuse ``ops`` and apply them to |0..0><0..0|; returns the DM handle."""
+    c = Circuit(n, ops)
+    f = c.fuse(max_width, prec, stream)
+    d = DM(n, prec, stream)
+    d.apply_fused(f)
+    f.free()
+    c.free()
+    return d

@@ -1,0 +1,115 @@
+"""C-ABI checks that need no GPU: the library loads and exports every declared symbol,
+host-side argument validation, and the fusion planner (Sec. 3.3) produces an exact
+reordering of the circuit, judged by the CPU oracle."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2404_13184_amd import tanq as T
+from paper_2404_13184_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "tanq.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:tanq_status|const char\*|int)\s+(tanq_\w+)\s*\(", text, re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(T.LIB_PATH):
+        from paper_2404_13184_amd import build_lib
+
+        build_lib.build()
+    return T.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    syms = declared_symbols()
+    assert len(syms) >= 25
+    for s in syms:
+        assert hasattr(lib, s), s
+    assert sorted(T.EXPORTED) == syms
+
+
+def test_version_and_error_text(lib):
+    assert T.tanq_version() >= 100
+    with pytest.raises(T.TanqError) as e:
+        T.tanq_circuit_create(0)
+    assert e.value.code == T.TANQ_E_ARG
+    assert "n must be" in T.tanq_last_error()
+
+
+def test_circuit_validation(lib):
+    c = T.tanq_circuit_create(3)
+    try:
+        T.tanq_circuit_add_gate(c, [0], W.hadamard())
+        for bad in ([0, 0], [3], [-1], [0, 1, 2, 0]):
+            with pytest.raises(T.TanqError) as e:
+                U = np.eye(2 ** len(bad))
+                T.tanq_circuit_add_gate(c, bad, U)
+            assert e.value.code == T.TANQ_E_ARG
+        T.tanq_circuit_add_kraus(c, [2, 1], np.stack(W.depolarizing(0.1, 2)))
+        assert T.tanq_circuit_size(c) == 2
+        with pytest.raises(T.TanqError):
+            T.tanq_fuse_plan(c, 0, 2)  # AUTO needs the device cost model
+        with pytest.raises(T.TanqError):
+            T.tanq_fuse_plan(c, 4, 2)
+    finally:
+        T.tanq_circuit_free(c)
+
+
+def test_null_handles_rejected(lib):
+    for fn in (lib.tanq_dm_reset, lib.tanq_sync, lib.tanq_dm_free):
+        rc = fn(None)
+        assert rc in (T.TANQ_OK, T.TANQ_E_ARG)  # free(NULL) is a no-op
+    assert lib.tanq_dm_reset(None) == T.TANQ_E_ARG
+    assert lib.tanq_apply_fused(None, None) == T.TANQ_E_ARG
+
+
+def plan_order(circ_ops, n, mode):
+    c = T.Circuit(n, circ_ops)
+    blocks, nb = c.plan(mode)
+    c.free()
+    order = sorted(range(len(circ_ops)), key=lambda i: (blocks[i], i))
+    return blocks, nb, order
+
+
+@pytest.mark.parametrize("mode", [T.TANQ_FUSE_NONE, T.TANQ_FUSE_PAPER, 1, 2, 3])
+def test_fusion_plan_is_exact_reordering(lib, oracle_mod, mode):
+    rng = np.random.default_rng(40 + mode)
+    n = 5
+    ops = []
+    for _ in range(40):
+        j = int(rng.choice([1, 1, 2, 2, 3]))
+        qs = tuple(int(x) for x in rng.choice(n, size=j, replace=False))
+        ops.append(W.channel([W.random_unitary(rng, 1 << j) * 0.9, np.eye(1 << j) * 0.3], qs))
+    blocks, nb, order = plan_order(ops, n, mode)
+    assert sorted(set(blocks)) == list(range(nb))
+    want = oracle_mod.run(n, ops)
+    got = oracle_mod.run(n, [ops[i] for i in order])
+    assert np.abs(got - want).max() <= 1e-12
+    # width and shape rules
+    for b in range(nb):
+        members = [ops[i] for i in range(len(ops)) if blocks[i] == b]
+        qs = set(q for op in members for q in op.qubits)
+        if mode == T.TANQ_FUSE_NONE:
+            assert len(members) == 1
+        elif mode == T.TANQ_FUSE_PAPER:
+            assert len({op.qubits for op in members}) == 1
+        else:
+            assert len(qs) <= max(mode, max(op.width for op in members))
+
+
+def test_fusion_ratio_on_workloads(lib):
+    n, ops = W.config4(layers=10)
+    _, nb2, _ = plan_order(ops, n, 2)
+    _, nb3, _ = plan_order(ops, n, 3)
+    _, nbp, _ = plan_order(ops, n, T.TANQ_FUSE_PAPER)
+    # 10 layers of 16 U3 + 16 dep + 8 CX + 8 dep2 = 480 operations
+    assert len(ops) == 480
+    assert nb3 <= nb2 < nbp < len(ops)
+    assert nb2 <= 10 * 8 + 16  # one block per CX pair plus stragglers
