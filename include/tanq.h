@@ -181,6 +181,32 @@ tanq_status tanq_apply_fused(tanq_dm d, tanq_fused f);
 tanq_status tanq_apply_fused_range(tanq_dm d, tanq_fused f, int begin, int end);
 
 /* ---------------------------------------------------------------------------------------
+ * Autotuning of the apply kernels (tile shape and workgroup size per width and precision).
+ * ------------------------------------------------------------------------------------- */
+
+typedef struct {
+  int k;          /* superoperator width (2 or 3) */
+  int prec;       /* tanq_prec */
+  int tile_bits;  /* log2 of the elements one workgroup stages per tile */
+  int threads;    /* workgroup size */
+} tanq_variant_t;
+
+/* Number of apply-kernel variants for width k (2 or 3) and precision p; k = 1 has one. */
+tanq_status tanq_variant_count(int k, tanq_prec p, int* count);
+tanq_status tanq_variant_get(int k, tanq_prec p, int index, tanq_variant_t* out);
+/* Process-wide choice used by every later apply of that width and precision. */
+tanq_status tanq_variant_select(int k, tanq_prec p, int index);
+tanq_status tanq_variant_selected(int k, tanq_prec p, int* index);
+
+/* Time every variant of every width k <= min(3, n) on d (reps applies of the identity
+ * superoperator on a low and a high qubit placement, so finite contents of d are left
+ * unchanged), select the fastest of each width, and record the best milliseconds per apply
+ * for (n, precision).  TANQ_FUSE_AUTO then chooses the fusion width that minimises the sum of
+ * these costs over the planned blocks.  ms_per_apply (may be NULL) receives 4 values, index
+ * k = 1..3 (0 where k > n).  Synchronises. */
+tanq_status tanq_autotune(tanq_dm d, int reps, double* ms_per_apply);
+
+/* ---------------------------------------------------------------------------------------
  * Measurement statistics (Sec. 2.1: rho gives the probability of every outcome).
  * ------------------------------------------------------------------------------------- */
 

@@ -399,12 +399,18 @@ tanq_status tanq_circuit_size(tanq_circuit c, int* count) {
 
 namespace {
 
-// Relative cost of one apply of width k, in units of one HBM pass over vec(rho), used
-// to choose the fusion width when asked to.  k <= 2 is bound by the HBM pass; k = 3 by
-// MFMA throughput (16 flop/B in FP64, 32 flop/B in FP32 against the machine balance).
-double apply_cost(int k, tanq_prec p) {
+// Measured milliseconds per apply, per (n, precision, k), filled by tanq_autotune.
+double g_cost_ms[MAX_N + 1][2][4] = {};
+
+// Cost of one apply of width k, used to choose the fusion width when asked to: the
+// autotuned time if there is one for (n, precision), else a model in units of one HBM
+// pass over vec(rho) -- k <= 2 is bound by that pass, k = 3 by MFMA throughput (16 flop/B
+// in FP64 and 32 flop/B in FP32 against machine balances of about 10 and 20 flop/B).
+double apply_cost(int n, int k, tanq_prec p) {
+  const double ms = g_cost_ms[n][p == TANQ_F64 ? 0 : 1][k];
+  if (ms > 0.0) return ms;
   if (k <= 2) return 1.0;
-  return p == TANQ_F64 ? 1.65 : 1.65;
+  return 1.65;
 }
 
 }  // namespace
@@ -429,7 +435,7 @@ tanq_status tanq_fuse(tanq_circuit c, int max_width, tanq_prec p, void* hip_stre
       for (int w = 2; w <= std::min(3, n); ++w) {
         std::vector<PlanBlock> pl = plan_fusion(pops, n, w);
         double cost = 0.0;
-        for (auto& b : pl) cost += apply_cost((int)b.qubits.size(), p);
+        for (auto& b : pl) cost += apply_cost(n, (int)b.qubits.size(), p);
         if (cost < best) {
           best = cost;
           plan = std::move(pl);
@@ -631,6 +637,127 @@ tanq_status tanq_apply_fused_range(tanq_dm d, tanq_fused f, int begin, int end) 
 tanq_status tanq_apply_fused(tanq_dm d, tanq_fused f) {
   if (!f) return set_error(TANQ_E_ARG, "fused handle is NULL");
   return tanq_apply_fused_range(d, f, 0, (int)f->blocks.size());
+}
+
+// ---------------------------------------------------------------------------------------
+// autotuning
+// ---------------------------------------------------------------------------------------
+
+tanq_status tanq_variant_count(int k, tanq_prec p, int* count) {
+  return guarded([&] {
+    if (!count) fail(TANQ_E_ARG, "count is NULL");
+    check_prec(p);
+    if (k == 1) {
+      *count = 1;
+      return;
+    }
+    if (k != 2 && k != 3) fail(TANQ_E_ARG, "k must be 1, 2 or 3");
+    *count = variant_count(k, p);
+  });
+}
+
+tanq_status tanq_variant_get(int k, tanq_prec p, int index, tanq_variant_t* out) {
+  return guarded([&] {
+    if (!out) fail(TANQ_E_ARG, "out is NULL");
+    check_prec(p);
+    if (k == 1) {
+      if (index != 0) fail(TANQ_E_ARG, "k = 1 has one variant");
+      *out = tanq_variant_t{1, (int)p, 0, 256};
+      return;
+    }
+    int tb = 0, th = 0;
+    if ((k != 2 && k != 3) || !variant_describe(k, p, index, &tb, &th)) fail(TANQ_E_ARG, "no such variant");
+    *out = tanq_variant_t{k, (int)p, tb, th};
+  });
+}
+
+tanq_status tanq_variant_select(int k, tanq_prec p, int index) {
+  return guarded([&] {
+    check_prec(p);
+    if (k == 1) {
+      if (index != 0) fail(TANQ_E_ARG, "k = 1 has one variant");
+      return;
+    }
+    if ((k != 2 && k != 3) || !variant_select(k, p, index)) fail(TANQ_E_ARG, "no such variant");
+  });
+}
+
+tanq_status tanq_variant_selected(int k, tanq_prec p, int* index) {
+  return guarded([&] {
+    if (!index) fail(TANQ_E_ARG, "index is NULL");
+    check_prec(p);
+    if (k == 1) {
+      *index = 0;
+      return;
+    }
+    if (k != 2 && k != 3) fail(TANQ_E_ARG, "k must be 1, 2 or 3");
+    *index = variant_selected(k, p);
+  });
+}
+
+tanq_status tanq_autotune(tanq_dm d, int reps, double* ms_per_apply) {
+  return guarded([&] {
+    check_dm(d);
+    if (reps < 1) fail(TANQ_E_ARG, "reps must be >= 1");
+    DeviceGuard g(d->device);
+    const int n = d->n;
+    const tanq_prec p = d->prec;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    TANQ_HIP(hipEventCreate(&e0));
+    TANQ_HIP(hipEventCreate(&e1));
+    double best_ms[4] = {0, 0, 0, 0};
+    try {
+      for (int k = 1; k <= std::min(3, n); ++k) {
+        // identity superoperator, packed for this precision in slot 0 of the handle
+        const int D = 1 << (2 * k);
+        std::vector<double> S((size_t)D * D * 2, 0.0);
+        for (int a = 0; a < D; ++a) S[2 * ((size_t)a * D + a)] = 1.0;
+        double* raw = d->s_raw_dev;
+        unsigned char* packed = d->s_packed_dev;
+        TANQ_HIP(hipStreamSynchronize(d->stream));
+        TANQ_HIP(hipMemcpy(raw, S.data(), S.size() * sizeof(double), hipMemcpyHostToDevice));
+        launch_pack_one(k, raw, packed, p, d->stream);
+        int lo[3], hi[3];
+        for (int t = 0; t < k; ++t) {
+          lo[t] = t;
+          hi[t] = n - k + t;
+        }
+        const int nvar = (k == 1) ? 1 : variant_count(k, p);
+        const int keep = (k == 1) ? 0 : variant_selected(k, p);
+        int best = keep;
+        double best_t = 1e300;
+        for (int v = 0; v < nvar; ++v) {
+          if (k > 1) variant_select(k, p, v);
+          launch_apply(d->ptr, n, p, k, lo, packed, d->stream);  // warm-up
+          TANQ_HIP(hipEventRecord(e0, d->stream));
+          for (int r = 0; r < reps; ++r) {
+            launch_apply(d->ptr, n, p, k, lo, packed, d->stream);
+            launch_apply(d->ptr, n, p, k, hi, packed, d->stream);
+          }
+          TANQ_HIP(hipEventRecord(e1, d->stream));
+          TANQ_HIP(hipEventSynchronize(e1));
+          float ms = 0.f;
+          TANQ_HIP(hipEventElapsedTime(&ms, e0, e1));
+          const double per = (double)ms / (2.0 * reps);
+          if (per < best_t) {
+            best_t = per;
+            best = v;
+          }
+        }
+        if (k > 1) variant_select(k, p, best);
+        best_ms[k] = best_t;
+        g_cost_ms[n][p == TANQ_F64 ? 0 : 1][k] = best_t;
+      }
+    } catch (...) {
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      throw;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (ms_per_apply)
+      for (int k = 0; k < 4; ++k) ms_per_apply[k] = best_ms[k];
+  });
 }
 
 // ---------------------------------------------------------------------------------------

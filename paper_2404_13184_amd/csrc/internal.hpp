@@ -83,8 +83,13 @@ constexpr int packed_elems(int k) { return k == 1 ? 32 : (k == 2 ? 32 * 32 : 128
 // launchers (kernels.hip)
 // ------------------------------------------------------------------------------------
 
-ApplyGeom make_apply_geom(int n, int k, const int* qubits_sorted_order, int vbits);
-int default_tile_bits(int k, tanq_prec p);
+ApplyGeom make_apply_geom(int n, int k, const int* qubits, int vbits);
+
+// Apply-kernel variants per (k, precision), k in {2, 3}: count, shape, process-wide choice.
+int variant_count(int k, tanq_prec p);
+bool variant_describe(int k, tanq_prec p, int index, int* tile_bits, int* threads);
+bool variant_select(int k, tanq_prec p, int index);
+int variant_selected(int k, tanq_prec p);
 
 void launch_init_zero(void* rho, int n, tanq_prec p, hipStream_t s);
 void launch_gather(const void* rho, tanq_prec p, const uint64_t* idx_dev, size_t count, void* out_dev,

@@ -90,12 +90,15 @@ __device__ inline void write_outputs(T* ldsT, const Acc& acc, const uint32_t* tj
   }
 }
 
-template <typename T, int K, int VMAX, int NT>
+// FULL: the tile has all 2^VMAX elements (every register size but the smallest), so the
+// load/store phases are straight-line code with no per-slot guards; that lets the compiler
+// wait only for the prefetched loads at the top of the loop and leave the previous tile's
+// stores in flight.
+template <typename T, int K, int VMAX, int NT, bool FULL>
 __global__ __launch_bounds__(NT) void apply_mfma_kernel(T* __restrict__ rho, const T* __restrict__ frag,
                                                         const ApplyGeom g) {
   using M = Mfma<T>;
   using acc_t = typename M::acc_t;
-  using c2 = typename M::c2;
   constexpr int NW = NT / 64;
   constexpr int D = 1 << (2 * K);  // superoperator dimension (complex)
   constexpr int R2 = 2 * D;        // real-block dimension
@@ -114,7 +117,7 @@ __global__ __launch_bounds__(NT) void apply_mfma_kernel(T* __restrict__ rho, con
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int slots = (1 << g.V) / EPS;
+  const int slots = FULL ? SLOTS : (1 << g.V) / EPS;
 
   // element offset of each 16-byte slot this thread moves (identical for every tile)
   uint64_t off[ITERS];
@@ -122,7 +125,7 @@ __global__ __launch_bounds__(NT) void apply_mfma_kernel(T* __restrict__ rho, con
   for (int it = 0; it < ITERS; ++it) {
     const uint32_t j = (uint32_t)((it * NT + tid) * EPS);
     uint64_t o = 0;
-    for (int b = 0; b < g.V; ++b) o |= (uint64_t)((j >> b) & 1u) << g.vpos[b];
+    for (int b = 0; b < (FULL ? VMAX : g.V); ++b) o |= (uint64_t)((j >> b) & 1u) << g.vpos[b];
     off[it] = o;
   }
 
@@ -139,21 +142,43 @@ __global__ __launch_bounds__(NT) void apply_mfma_kernel(T* __restrict__ rho, con
   const int hb = (lane >> 5) & 1;          // low bit of the B row's complex index
   const int cc = (lane >> 4) & 1;          // re / im of the B row
   const uint32_t tj1 = hb ? g.tj[1] : 0u;  // tile-local part contributed by that bit
-  const uint32_t tq = g.tj[2 * (lane >> 4)];  // output rows 2*(lane>>4) (+1) of each m-tile
+  const uint32_t tq = g.tj[2 * (lane >> 4)];  // f32 output rows 4*(lane>>4) .. +3
 
-  for (uint64_t tile = blockIdx.x; tile < g.ntiles; tile += gridDim.x) {
-    uint64_t base = 0;
-    for (int r = 0; r < g.nruns; ++r)
-      base |= ((tile >> g.run_src[r]) & ((1ull << g.run_len[r]) - 1ull)) << g.run_dst[r];
+  // constant indices keep the run table in scalar registers (loaded once)
+  auto tile_base = [&](uint64_t tile) {
+    uint64_t b = 0;
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+      if (r < g.nruns) b |= ((tile >> g.run_src[r]) & ((1ull << g.run_len[r]) - 1ull)) << g.run_dst[r];
+    return b;
+  };
 
-    u32x4 buf[ITERS];
+  // Software pipeline: the next tile's global loads are in flight while this tile is
+  // multiplied and written back.  The loop is rotated so that the wait for those loads
+  // comes after this tile's stores have been issued: the vector-memory counter then only
+  // has to drain to the number of stores, and the stores overlap the next tile's work.
+  uint64_t tile = blockIdx.x;
+  if (tile >= g.ntiles) return;  // uniform per workgroup
+  uint64_t cur = tile_base(tile);
+  u32x4 buf[ITERS];
 #pragma unroll
-    for (int it = 0; it < ITERS; ++it)
-      if (it * NT + tid < slots) buf[it] = *reinterpret_cast<const u32x4*>(rho + 2 * (base + off[it]));
+  for (int it = 0; it < ITERS; ++it)
+    if (FULL || it * NT + tid < slots) buf[it] = *reinterpret_cast<const u32x4*>(rho + 2 * (cur + off[it]));
 #pragma unroll
-    for (int it = 0; it < ITERS; ++it)
-      if (it * NT + tid < slots) lds[it * NT + tid] = buf[it];
-    __syncthreads();
+  for (int it = 0; it < ITERS; ++it)
+    if (FULL || it * NT + tid < slots) lds[it * NT + tid] = buf[it];
+  __syncthreads();
+
+  for (;;) {
+    const uint64_t next = tile + gridDim.x;
+    const bool more = next < g.ntiles;
+    uint64_t nbase = 0;
+    if (more) {
+      nbase = tile_base(next);
+#pragma unroll
+      for (int it = 0; it < ITERS; ++it)
+        if (FULL || it * NT + tid < slots) buf[it] = *reinterpret_cast<const u32x4*>(rho + 2 * (nbase + off[it]));
+    }
 
     if constexpr (K == 2) {
       for (int nb = wave; nb < nblk; nb += NW) {
@@ -212,11 +237,15 @@ __global__ __launch_bounds__(NT) void apply_mfma_kernel(T* __restrict__ rho, con
 
 #pragma unroll
     for (int it = 0; it < ITERS; ++it)
-      if (it * NT + tid < slots) buf[it] = lds[it * NT + tid];
+      if (FULL || it * NT + tid < slots) *reinterpret_cast<u32x4*>(rho + 2 * (cur + off[it])) = lds[it * NT + tid];
+    if (!more) break;
+    __syncthreads();  // every store-phase LDS read is done before the next tile lands
 #pragma unroll
     for (int it = 0; it < ITERS; ++it)
-      if (it * NT + tid < slots) *reinterpret_cast<u32x4*>(rho + 2 * (base + off[it])) = buf[it];
+      if (FULL || it * NT + tid < slots) lds[it * NT + tid] = buf[it];
     __syncthreads();
+    tile = next;
+    cur = nbase;
   }
 }
 
@@ -525,11 +554,6 @@ int device_cu_count() {
   return cached;
 }
 
-int default_tile_bits(int k, tanq_prec p) {
-  if (k == 2) return p == TANQ_F64 ? 10 : 11;
-  return 12;
-}
-
 ApplyGeom make_apply_geom(int n, int k, const int* q, int vbits) {
   ApplyGeom g;
   std::memset(&g, 0, sizeof(g));
@@ -601,9 +625,9 @@ static int persistent_grid(KernelT kernel, int threads, uint64_t ntiles) {
   return (int)(ntiles < cap ? ntiles : cap);
 }
 
-template <typename T, int K, int VMAX, int NT>
-static void launch_mfma(T* rho, const ApplyGeom& g, const T* frag, hipStream_t s) {
-  auto kern = apply_mfma_kernel<T, K, VMAX, NT>;
+template <typename T, int K, int VMAX, int NT, bool FULL>
+static void launch_mfma_shape(const ApplyGeom& g, void* rho, const void* frag, hipStream_t s) {
+  auto kern = apply_mfma_kernel<T, K, VMAX, NT, FULL>;
   static thread_local int grid_cap_dev = -1;
   static thread_local uint64_t grid_cap = 0;
   int dev = 0;
@@ -613,9 +637,83 @@ static void launch_mfma(T* rho, const ApplyGeom& g, const T* frag, hipStream_t s
     grid_cap_dev = dev;
   }
   const uint64_t grid = g.ntiles < grid_cap ? g.ntiles : grid_cap;
-  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(NT), 0, s, rho, frag, g);
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(NT), 0, s, (T*)rho, (const T*)frag, g);
   TANQ_HIP(hipGetLastError());
 }
+
+template <typename T, int K, int VMAX, int NT>
+static void launch_mfma(void* rho, int n, const int* qubits, const void* frag, hipStream_t s) {
+  const ApplyGeom g = make_apply_geom(n, K, qubits, VMAX);
+  if (g.V == VMAX)
+    launch_mfma_shape<T, K, VMAX, NT, true>(g, rho, frag, s);
+  else
+    launch_mfma_shape<T, K, VMAX, NT, false>(g, rho, frag, s);
+}
+
+typedef void (*apply_fn)(void*, int, const int*, const void*, hipStream_t);
+
+struct VariantEntry {
+  int k;
+  tanq_prec p;
+  int tile_bits;
+  int threads;
+  apply_fn fn;
+};
+
+// Apply-kernel variants (tile shape x workgroup size); the first of each (k, precision) is
+// the default until the autotuner or the caller selects another.
+static const VariantEntry kVariants[] = {
+    {2, TANQ_F64, 10, 256, launch_mfma<double, 2, 10, 256>},
+    {2, TANQ_F64, 11, 256, launch_mfma<double, 2, 11, 256>},
+    {2, TANQ_F64, 11, 512, launch_mfma<double, 2, 11, 512>},
+    {2, TANQ_F64, 12, 512, launch_mfma<double, 2, 12, 512>},
+    {2, TANQ_F32, 11, 256, launch_mfma<float, 2, 11, 256>},
+    {2, TANQ_F32, 12, 256, launch_mfma<float, 2, 12, 256>},
+    {2, TANQ_F32, 12, 512, launch_mfma<float, 2, 12, 512>},
+    {2, TANQ_F32, 13, 512, launch_mfma<float, 2, 13, 512>},
+    {3, TANQ_F64, 12, 512, launch_mfma<double, 3, 12, 512>},
+    {3, TANQ_F64, 12, 256, launch_mfma<double, 3, 12, 256>},
+    {3, TANQ_F32, 12, 512, launch_mfma<float, 3, 12, 512>},
+    {3, TANQ_F32, 13, 512, launch_mfma<float, 3, 13, 512>},
+    {3, TANQ_F32, 12, 256, launch_mfma<float, 3, 12, 256>},
+};
+constexpr int kNumVariants = (int)(sizeof(kVariants) / sizeof(kVariants[0]));
+
+// selected variant per (k, precision), as an index among that pair's variants
+static int g_selected[4][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+
+static int variant_global_index(int k, tanq_prec p, int local) {
+  int c = 0;
+  for (int i = 0; i < kNumVariants; ++i)
+    if (kVariants[i].k == k && kVariants[i].p == p) {
+      if (c == local) return i;
+      ++c;
+    }
+  return -1;
+}
+
+int variant_count(int k, tanq_prec p) {
+  int c = 0;
+  for (int i = 0; i < kNumVariants; ++i)
+    if (kVariants[i].k == k && kVariants[i].p == p) ++c;
+  return c;
+}
+
+bool variant_describe(int k, tanq_prec p, int local, int* tile_bits, int* threads) {
+  const int gi = variant_global_index(k, p, local);
+  if (gi < 0) return false;
+  if (tile_bits) *tile_bits = kVariants[gi].tile_bits;
+  if (threads) *threads = kVariants[gi].threads;
+  return true;
+}
+
+bool variant_select(int k, tanq_prec p, int local) {
+  if (variant_global_index(k, p, local) < 0) return false;
+  g_selected[k][p == TANQ_F64 ? 0 : 1] = local;
+  return true;
+}
+
+int variant_selected(int k, tanq_prec p) { return g_selected[k][p == TANQ_F64 ? 0 : 1]; }
 
 void launch_apply(void* rho, int n, tanq_prec p, int k, const int* qubits, const void* packed, hipStream_t s) {
   if (k == 1) {
@@ -632,20 +730,9 @@ void launch_apply(void* rho, int n, tanq_prec p, int k, const int* qubits, const
     TANQ_HIP(hipGetLastError());
     return;
   }
-  const ApplyGeom g = make_apply_geom(n, k, qubits, default_tile_bits(k, p));
-  if (k == 2) {
-    if (p == TANQ_F64)
-      launch_mfma<double, 2, 10, 256>((double*)rho, g, (const double*)packed, s);
-    else
-      launch_mfma<float, 2, 11, 256>((float*)rho, g, (const float*)packed, s);
-  } else if (k == 3) {
-    if (p == TANQ_F64)
-      launch_mfma<double, 3, 12, 512>((double*)rho, g, (const double*)packed, s);
-    else
-      launch_mfma<float, 3, 12, 512>((float*)rho, g, (const float*)packed, s);
-  } else {
-    fail(TANQ_E_ARG, "superoperator width must be 1, 2 or 3");
-  }
+  if (k != 2 && k != 3) fail(TANQ_E_ARG, "superoperator width must be 1, 2 or 3");
+  const int gi = variant_global_index(k, p, variant_selected(k, p));
+  kVariants[gi].fn(rho, n, qubits, packed, s);
 }
 
 void launch_init_zero(void* rho, int n, tanq_prec p, hipStream_t s) {

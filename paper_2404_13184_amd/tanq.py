@@ -40,6 +40,7 @@ EXPORTED = [
     "tanq_circuit_size",
     "tanq_fuse", "tanq_fuse_plan", "tanq_fused_info", "tanq_fused_free", "tanq_fused_get",
     "tanq_apply_superop", "tanq_apply_fused", "tanq_apply_fused_range",
+    "tanq_variant_count", "tanq_variant_get", "tanq_variant_select", "tanq_variant_selected", "tanq_autotune",
     "tanq_probs", "tanq_expect_pauli", "tanq_expect_pauli_c", "tanq_expect_pauli_batch",
 ]
 
@@ -48,6 +49,10 @@ class TanqError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__("tanq error %d: %s" % (code, msg))
         self.code = code
+
+
+class Variant(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int), ("prec", ctypes.c_int), ("tile_bits", ctypes.c_int), ("threads", ctypes.c_int)]
 
 
 class FusedInfo(ctypes.Structure):
@@ -87,6 +92,11 @@ _SIGS = {
     "tanq_apply_superop": ([_vp, ctypes.c_int, _ip, _dp], ctypes.c_int),
     "tanq_apply_fused": ([_vp, _vp], ctypes.c_int),
     "tanq_apply_fused_range": ([_vp, _vp, ctypes.c_int, ctypes.c_int], ctypes.c_int),
+    "tanq_variant_count": ([ctypes.c_int, ctypes.c_int, _ip], ctypes.c_int),
+    "tanq_variant_get": ([ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(Variant)], ctypes.c_int),
+    "tanq_variant_select": ([ctypes.c_int, ctypes.c_int, ctypes.c_int], ctypes.c_int),
+    "tanq_variant_selected": ([ctypes.c_int, ctypes.c_int, _ip], ctypes.c_int),
+    "tanq_autotune": ([_vp, ctypes.c_int, _dp], ctypes.c_int),
     "tanq_probs": ([_vp, _dp, ctypes.c_int, _dp], ctypes.c_int),
     "tanq_expect_pauli": ([_vp, ctypes.c_char_p, _dp], ctypes.c_int),
     "tanq_expect_pauli_c": ([_vp, ctypes.c_char_p, _dp, _dp], ctypes.c_int),
@@ -273,6 +283,34 @@ def tanq_apply_fused_range(h: int, fused: int, begin: int, end: int):
     _check(load().tanq_apply_fused_range(h, fused, begin, end))
 
 
+def tanq_variant_count(k: int, prec: int) -> int:
+    c = ctypes.c_int()
+    _check(load().tanq_variant_count(k, prec, ctypes.byref(c)))
+    return c.value
+
+
+def tanq_variant_get(k: int, prec: int, index: int) -> dict:
+    v = Variant()
+    _check(load().tanq_variant_get(k, prec, index, ctypes.byref(v)))
+    return {"k": v.k, "prec": v.prec, "tile_bits": v.tile_bits, "threads": v.threads}
+
+
+def tanq_variant_select(k: int, prec: int, index: int):
+    _check(load().tanq_variant_select(k, prec, index))
+
+
+def tanq_variant_selected(k: int, prec: int) -> int:
+    c = ctypes.c_int()
+    _check(load().tanq_variant_selected(k, prec, ctypes.byref(c)))
+    return c.value
+
+
+def tanq_autotune(h: int, reps: int = 3) -> list:
+    ms = (ctypes.c_double * 4)()
+    _check(load().tanq_autotune(h, reps, ms))
+    return list(ms)
+
+
 def tanq_probs(h: int, dim: int, renormalize: bool = True):
     out = np.empty(dim, dtype=np.float64)
     tr = ctypes.c_double()
@@ -373,6 +411,9 @@ class DM:
 
     def probs(self, renormalize: bool = True):
         return tanq_probs(self.h, 1 << self.n, renormalize)
+
+    def autotune(self, reps: int = 3) -> list:
+        return tanq_autotune(self.h, reps)
 
     def expect_pauli(self, pauli: str) -> complex:
         return tanq_expect_pauli_c(self.h, pauli)
