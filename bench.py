@@ -42,12 +42,22 @@ def parse():
     return ap.parse_args()
 
 
-def run_precision(T, W, torch, n, ops, prec, width, steps, warmup):
-    """Time `steps` full passes; returns a dict of measurements."""
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def run_precision(T, torch, n, ops, prec, width, steps, warmup):
+    """Autotune, then time `steps` full passes of the hot path.  Returns (measurements, dm);
+    the caller frees the dm."""
     stream = torch.cuda.current_stream()
     circ = T.Circuit(n, ops)
     d = T.DM(n, prec, stream)
-    dim = 1 << n
+    t0 = time.perf_counter()
+    tuned_ms = d.autotune(reps=2)
+    d.reset()
+    variants = {k: T.tanq_variant_get(k, T._prec(prec), T.tanq_variant_selected(k, T._prec(prec)))
+                for k in (2, 3) if k <= n}
+    log("%s autotune %.1fs: ms/apply by k %s" % (prec, time.perf_counter() - t0, tuned_ms[1:]))
 
     def one_step(events=None):
         d.reset()
@@ -67,23 +77,24 @@ def run_precision(T, W, torch, n, ops, prec, width, steps, warmup):
         f.free()
         return info, p, tr
 
-    for _ in range(warmup):
+    for w in range(warmup):
         one_step()
+        log("%s warmup step %d done" % (prec, w + 1))
     torch.cuda.synchronize()
     events = []
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for st in range(steps):
         info, p, tr = one_step(events)
+        log("%s step %d done (%.1fs)" % (prec, st + 1, time.perf_counter() - t0))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     per_k = {}
     for k, e0, e1 in events:
         per_k.setdefault(k, []).append(e0.elapsed_time(e1) * 1e-3)
-    d.free()
     circ.free()
     applies = info["count"] * steps
-    return {"wall_s": wall, "applies": applies, "info": info, "per_k": per_k, "trace": tr,
-            "pmax": float(p.max()), "pmin": float(p.min())}
+    return {"wall_s": wall, "applies": applies, "info": info, "per_k": per_k, "trace": tr, "probs": p,
+            "tuned_ms": tuned_ms[1:], "variants": variants}, d
 
 
 def roofline(prec, k, n, secs):
@@ -138,6 +149,7 @@ def main():
         print("bench.py runs on one GPU only: this path has no multi-GPU sharding (use --gpus 1)",
               file=sys.stderr)
         sys.exit(2)
+    import numpy as np
     import torch
 
     from paper_2404_13184_amd import tanq as T
@@ -146,9 +158,19 @@ def main():
     T.load()
     torch.cuda.init()
     n, ops = W.config4(layers=a.layers, n=a.n)
-    results = {}
+    results, dms = {}, {}
     for prec in a.precs.split(","):
-        results[prec] = run_precision(T, W, torch, n, ops, prec, a.width, a.steps, a.warmup)
+        results[prec], dms[prec] = run_precision(T, torch, n, ops, prec, a.width, a.steps, a.warmup)
+    accuracy = None
+    if "f64" in dms and "f32" in dms:
+        fro, mx, nrm = dms["f32"].compare(dms["f64"])
+        dp = float(np.abs(results["f32"]["probs"] - results["f64"]["probs"]).max())
+        accuracy = {"fro_diff": fro, "max_abs_diff": mx, "fro_f64": nrm,
+                    "trace_distance_bound": 0.5 * (2 ** (n / 2)) * fro, "max_abs_dprob": dp}
+        log("f32 vs f64: ||d||_F %.3e, max %.3e, TD <= %.3e, max|dp| %.3e" %
+            (fro, mx, accuracy["trace_distance_bound"], dp))
+    for d in dms.values():
+        d.free()
 
     main_prec = "f64" if "f64" in results else a.precs.split(",")[0]
     r = results[main_prec]
@@ -187,8 +209,13 @@ def main():
                      "fused_applies": rr["info"]["count"], "fusion_width": rr["info"]["max_width"],
                      "count_by_k": rr["info"]["count_k"][1:],
                      "avg_launch_ms_by_k": {str(k): round(sum(v) / len(v) * 1e3, 3) for k, v in rr["per_k"].items()},
-                     "roofline": dominant(rr, prec), "trace": rr["trace"]}
+                     "roofline": dominant(rr, prec), "trace": rr["trace"],
+                     "autotuned_ms_per_apply_by_k": [round(x, 3) for x in rr["tuned_ms"]],
+                     "variants": rr["variants"]}
+    if accuracy is not None:
+        out["f32_vs_f64"] = accuracy
     if not a.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
         cb = cpu_baseline(W, n, a.layers, a.cpu_n, a.cpu_budget_s)
         gates_per_apply = len(ops) / r["info"]["count"]
         out["cpu_baseline"] = {

@@ -128,6 +128,14 @@ tanq_status tanq_circuit_add_gate(tanq_circuit c, int j, const int* qubits, cons
  * complex128 row-major matrices).  The channel is rho -> sum_i K_i rho K_i^dagger. */
 tanq_status tanq_circuit_add_kraus(tanq_circuit c, int j, const int* qubits, int m, const double* K);
 
+/* Append `count` operations at once.  Operation i acts on qubits[3i .. 3i + j[i] - 1] with
+ * m[i] Kraus matrices (2^j[i] x 2^j[i] complex128 row-major each; m[i] = 1 with a unitary is a
+ * gate) stored at pool[koff[i] ..] (offsets in doubles).  pool (pool_doubles doubles) is copied
+ * once and shared by the operations, so a channel repeated through a circuit costs one copy.
+ * All-or-nothing: on TANQ_E_ARG (bad width, qubit, count or offset) nothing is appended. */
+tanq_status tanq_circuit_add_ops(tanq_circuit c, int count, const int* j, const int* qubits, const int* m,
+                                 const int64_t* koff, const double* pool, size_t pool_doubles);
+
 /* Number of operations appended so far. */
 tanq_status tanq_circuit_size(tanq_circuit c, int* count);
 
@@ -226,6 +234,86 @@ tanq_status tanq_expect_pauli_c(tanq_dm d, const char* pauli, double* re, double
  * (out_im may be NULL). */
 tanq_status tanq_expect_pauli_batch(tanq_dm d, int count, const char* const* paulis, double* out_re,
                                     double* out_im);
+
+/* Compare two density matrices of the same n (any precisions), reduced in FP64 on the GPU:
+ * out[0] = ||a - b||_F, out[1] = max_ij |a_ij - b_ij|, out[2] = ||a||_F.  The trace distance
+ * obeys (1/2)||a - b||_1 <= (1/2) 2^(n/2) ||a - b||_F.  Both handles must live on the same
+ * device; work is ordered on a's stream after b's stream is synchronised.  Synchronises. */
+tanq_status tanq_dm_compare(tanq_dm a, tanq_dm b, double* out3);
+
+/* ---------------------------------------------------------------------------------------
+ * Serving: continuous batching of many small noisy circuits.
+ *
+ * Requests are admitted in arrival order while a slot is free and their device footprint
+ * (vec(rho) plus packed superoperators plus fusion temporaries, known at submit) fits in the
+ * budget.  Each admitted request's state stays resident on the device until its results are
+ * read back.  A scheduler thread applies, per batched launch, the next fused superoperator of
+ * every resident request at once (steps_per_launch such launches per iteration, optionally
+ * captured once in a hipGraph and replayed); requests arriving meanwhile join at the next
+ * iteration.  A request's arithmetic does not depend on the other requests in the batch, so
+ * its results are the same alone and in the mix.  All blocks are widened to the server's
+ * fusion width (2 or 3).  Errors on the scheduler thread fail the affected requests with
+ * TANQ_E_HIP and the server stops accepting work.
+ * ------------------------------------------------------------------------------------- */
+
+typedef struct tanq_server_s* tanq_server;
+
+typedef struct {
+  size_t hbm_budget;    /* device bytes the server may use for states and operands (>= 64 MiB) */
+  int max_slots;        /* requests resident at once, 1..4096 */
+  int prec;             /* tanq_prec of the states */
+  int width;            /* fusion width 2 or 3 (0 = 2) */
+  int steps_per_launch; /* batched applies per scheduler iteration, 1..64 */
+  int use_graphs;       /* nonzero: replay the iteration's launches from a captured hipGraph */
+} tanq_server_config;
+
+typedef struct {
+  int probs;                 /* nonzero: return the 2^n probabilities, divided by the trace */
+  int npauli;                /* number of Pauli strings (0..1024) */
+  const char* const* paulis; /* n characters of "IXYZ" each, character t acting on qubit t */
+} tanq_outputs;
+
+typedef struct {
+  int status;            /* TANQ_OK or the request's error */
+  int n;
+  double trace;
+  const double* probs;   /* 2^n values or NULL; owned by the server until release */
+  const double* pauli;   /* npauli values Re Tr(P rho) */
+  int npauli;
+  int fused_applies;     /* fused superoperators applied */
+  double t_submit, t_admit, t_done; /* seconds on the server clock */
+} tanq_result;
+
+typedef struct {
+  uint64_t submitted, admitted, completed, rejected;
+  uint64_t launches;     /* scheduler iterations (each steps_per_launch batched applies) */
+  uint64_t steps;        /* batched applies that had work */
+  size_t bytes_in_use, peak_bytes, budget_bytes;
+  int active, pending;
+  double clock;          /* seconds since creation */
+} tanq_server_stats;
+
+/* Create a server on the current device with its own stream and scheduler thread.
+ * TANQ_E_OOM if the budget exceeds free device memory. */
+tanq_status tanq_server_create(const tanq_server_config* cfg, tanq_server* out);
+
+/* Queue a circuit (copied; c may be freed afterwards) with the outputs wanted.  Never blocks on
+ * the GPU: plans the fusion on the calling thread and returns a ticket.  TANQ_E_ARG if n is
+ * outside [width, 14]; TANQ_E_OOM if the request alone exceeds the budget (it could never be
+ * admitted). */
+tanq_status tanq_server_submit(tanq_server s, tanq_circuit c, const tanq_outputs* outs, uint64_t* ticket);
+
+/* Result of a finished request (TANQ_E_AGAIN while it is not finished); wait blocks. */
+tanq_status tanq_server_poll(tanq_server s, uint64_t ticket, tanq_result* out);
+tanq_status tanq_server_wait(tanq_server s, uint64_t ticket, tanq_result* out);
+
+/* Drop a finished request and its result buffers. */
+tanq_status tanq_server_release(tanq_server s, uint64_t ticket);
+
+tanq_status tanq_server_stats_get(tanq_server s, tanq_server_stats* out);
+
+/* Finish queued work, stop the scheduler and free everything. */
+tanq_status tanq_server_destroy(tanq_server s);
 
 #ifdef __cplusplus
 }

@@ -7,42 +7,30 @@
 #include <string>
 #include <vector>
 
-#include "fuse_plan.hpp"
-#include "internal.hpp"
+#include "abi_util.hpp"
+#include "circuit.hpp"
 
 using namespace tanq;
 
 namespace {
-
 thread_local std::string g_last_error;
+}  // namespace
 
-tanq_status set_error(tanq_status code, const std::string& msg) {
+namespace tanq {
+tanq_status set_last_error(tanq_status code, const std::string& msg) {
   g_last_error = msg;
   return code;
 }
+void clear_last_error() { g_last_error.clear(); }
+}  // namespace tanq
 
-template <typename F>
-tanq_status guarded(F&& f) {
-  try {
-    g_last_error.clear();
-    f();
-    return TANQ_OK;
-  } catch (const Error& e) {
-    return set_error(e.code, e.what());
-  } catch (const std::bad_alloc&) {
-    return set_error(TANQ_E_OOM, "host allocation failed");
-  } catch (const std::exception& e) {
-    return set_error(TANQ_E_STATE, e.what());
-  } catch (...) {
-    return set_error(TANQ_E_STATE, "unknown failure");
-  }
-}
+namespace {
+
+tanq_status set_error(tanq_status code, const std::string& msg) { return set_last_error(code, msg); }
 
 constexpr int MAX_N = 17;
 constexpr int RING = 8;
 constexpr size_t SLOT_DOUBLES = 2 * 64 * 64;  // one 3-qubit superoperator, complex128
-
-size_t elem_size(tanq_prec p) { return p == TANQ_F64 ? 16 : 8; }
 
 void check_prec(tanq_prec p) {
   if (p != TANQ_F64 && p != TANQ_F32) fail(TANQ_E_ARG, "precision must be TANQ_F64 or TANQ_F32");
@@ -58,13 +46,6 @@ void check_qubits(int n, int k, const int* q, int kmax) {
       if (q[u] == q[t]) fail(TANQ_E_ARG, "duplicate qubit " + std::to_string(q[t]));
   }
 }
-
-size_t packed_bytes(int k, tanq_prec p) {
-  if (k == 1) return 32 * sizeof(double);
-  return (size_t)packed_elems(k) * (p == TANQ_F64 ? sizeof(double) : sizeof(float));
-}
-
-size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct DeviceGuard {
   int prev = -1;
@@ -105,25 +86,6 @@ struct tanq_dm_s {
 
   uint64_t elements() const { return 1ull << (2 * n); }
   size_t bytes() const { return (size_t)elements() * elem_size(prec); }
-};
-
-struct HostOp {
-  int j = 0;
-  int m = 0;
-  int q[3] = {0, 0, 0};
-  std::vector<double> K;  // m matrices, 2^j x 2^j complex row-major
-};
-
-struct tanq_circuit_s {
-  int n = 0;
-  std::vector<HostOp> ops;
-};
-
-struct FusedBlockHost {
-  int k = 0;
-  int qubits[3] = {0, 0, 0};
-  size_t raw_off = 0;   // complex elements
-  size_t pack_off = 0;  // bytes
 };
 
 struct tanq_fused_s {
@@ -374,7 +336,8 @@ static void add_op(tanq_circuit c, int j, const int* qubits, int m, const double
   op.m = m;
   for (int t = 0; t < j; ++t) op.q[t] = qubits[t];
   const size_t cnt = (size_t)m * (1u << j) * (1u << j) * 2;
-  op.K.assign(K, K + cnt);
+  op.pool = std::make_shared<const std::vector<double>>(K, K + cnt);
+  op.koff = 0;
   c->ops.push_back(std::move(op));
 }
 
@@ -384,6 +347,31 @@ tanq_status tanq_circuit_add_gate(tanq_circuit c, int j, const int* qubits, cons
 
 tanq_status tanq_circuit_add_kraus(tanq_circuit c, int j, const int* qubits, int m, const double* K) {
   return guarded([&] { add_op(c, j, qubits, m, K); });
+}
+
+tanq_status tanq_circuit_add_ops(tanq_circuit c, int count, const int* j, const int* qubits, const int* m,
+                                 const int64_t* koff, const double* pool, size_t pool_doubles) {
+  return guarded([&] {
+    if (!c) fail(TANQ_E_ARG, "circuit handle is NULL");
+    if (count < 0) fail(TANQ_E_ARG, "count must be >= 0");
+    if (count == 0) return;
+    if (!j || !qubits || !m || !koff || !pool) fail(TANQ_E_ARG, "NULL argument");
+    auto shared = std::make_shared<const std::vector<double>>(pool, pool + pool_doubles);
+    std::vector<HostOp> add((size_t)count);
+    for (int i = 0; i < count; ++i) {
+      check_qubits(c->n, j[i], qubits + 3 * i, 3);
+      if (m[i] < 1) fail(TANQ_E_ARG, "at least one Kraus matrix is required");
+      HostOp& op = add[i];
+      op.j = j[i];
+      op.m = m[i];
+      for (int t = 0; t < op.j; ++t) op.q[t] = qubits[3 * i + t];
+      if (koff[i] < 0 || (size_t)koff[i] + op.kdoubles() > pool_doubles)
+        fail(TANQ_E_ARG, "operation " + std::to_string(i) + " reads past the matrix pool");
+      op.pool = shared;
+      op.koff = (size_t)koff[i];
+    }
+    c->ops.insert(c->ops.end(), std::make_move_iterator(add.begin()), std::make_move_iterator(add.end()));
+  });
 }
 
 tanq_status tanq_circuit_size(tanq_circuit c, int* count) {
@@ -423,11 +411,7 @@ tanq_status tanq_fuse(tanq_circuit c, int max_width, tanq_prec p, void* hip_stre
     if (max_width < -2 || max_width > 3) fail(TANQ_E_ARG, "max_width must be -2..3");
     hipStream_t s = (hipStream_t)hip_stream;
     const int n = c->n;
-    std::vector<PlanOp> pops(c->ops.size());
-    for (size_t i = 0; i < c->ops.size(); ++i) {
-      pops[i].j = c->ops[i].j;
-      for (int t = 0; t < 3; ++t) pops[i].q[t] = c->ops[i].q[t];
-    }
+    const std::vector<PlanOp> pops = plan_ops(c->ops);
     int mode = max_width;
     std::vector<PlanBlock> plan;
     if (mode == TANQ_FUSE_AUTO) {
@@ -456,51 +440,9 @@ tanq_status tanq_fuse(tanq_circuit c, int max_width, tanq_prec p, void* hip_stre
     f->mode = mode;
     f->source_ops = (int)c->ops.size();
     TANQ_HIP(hipGetDevice(&f->device));
-
-    // host tables
-    std::vector<FuseOpDev> opt;
-    std::vector<FuseBlockDev> blt;
-    std::vector<double> kraus;
-    size_t sop_total = 0, raw_total = 0, pack_total = 0;
-    int max_k = 1;
-    for (auto& pb : plan) {
-      const int k = (int)pb.qubits.size();
-      if (k > 3) fail(TANQ_E_UNSUPPORTED, "a block wider than 3 qubits");
-      max_k = std::max(max_k, k);
-      FuseBlockDev bd{};
-      bd.k = k;
-      bd.op_begin = (int)opt.size();
-      bd.op_count = (int)pb.ops.size();
-      bd.out_off = (int64_t)raw_total;
-      bd.pack_off = (int64_t)pack_total;
-      FusedBlockHost bh;
-      bh.k = k;
-      for (int t = 0; t < k; ++t) bh.qubits[t] = pb.qubits[t];
-      bh.raw_off = raw_total;
-      bh.pack_off = pack_total;
-      raw_total += (size_t)1 << (4 * k);
-      pack_total += align256(packed_bytes(k, p));
-      for (int oi : pb.ops) {
-        const HostOp& ho = c->ops[oi];
-        FuseOpDev od{};
-        od.j = ho.j;
-        od.m = ho.m;
-        od.kraus_off = (int64_t)(kraus.size() / 2);
-        od.sop_off = (int64_t)sop_total;
-        for (int t = 0; t < ho.j; ++t) {
-          int pos = -1;
-          for (int u = 0; u < k; ++u)
-            if (pb.qubits[u] == ho.q[t]) pos = u;
-          od.pos[t] = pos;
-        }
-        kraus.insert(kraus.end(), ho.K.begin(), ho.K.end());
-        sop_total += (size_t)1 << (4 * ho.j);
-        opt.push_back(od);
-      }
-      blt.push_back(bd);
-      f->blocks.push_back(bh);
-      f->count_k[k] += 1;
-    }
+    const FuseLayout L = make_fuse_layout(c->ops, plan, p);
+    f->blocks = L.host;
+    for (int k = 0; k < 4; ++k) f->count_k[k] = L.count_k[k];
 
     if (!plan.empty()) {
       FuseOpDev* d_ops = nullptr;
@@ -513,18 +455,16 @@ tanq_status tanq_fuse(tanq_circuit c, int max_width, tanq_prec p, void* hip_stre
         dfree(d_sops);
       };
       try {
-        TANQ_HIP(hipMalloc((void**)&d_ops, opt.size() * sizeof(FuseOpDev)));
-        TANQ_HIP(hipMalloc((void**)&d_blk, blt.size() * sizeof(FuseBlockDev)));
-        TANQ_HIP(hipMalloc((void**)&d_kraus, kraus.size() * sizeof(double)));
-        TANQ_HIP(hipMalloc((void**)&d_sops, sop_total * 2 * sizeof(double)));
-        TANQ_HIP(hipMalloc((void**)&f->raw, raw_total * 2 * sizeof(double)));
-        TANQ_HIP(hipMalloc((void**)&f->packed, pack_total));
-        TANQ_HIP(hipMemcpyAsync(d_ops, opt.data(), opt.size() * sizeof(FuseOpDev), hipMemcpyHostToDevice, s));
-        TANQ_HIP(hipMemcpyAsync(d_blk, blt.data(), blt.size() * sizeof(FuseBlockDev), hipMemcpyHostToDevice, s));
-        TANQ_HIP(hipMemcpyAsync(d_kraus, kraus.data(), kraus.size() * sizeof(double), hipMemcpyHostToDevice, s));
-        launch_build_superops(d_ops, (int)opt.size(), d_kraus, d_sops, s);
-        launch_compose(d_blk, (int)blt.size(), max_k, d_ops, d_sops, f->raw, s);
-        launch_pack(d_blk, (int)blt.size(), f->raw, f->packed, p, s);
+        TANQ_HIP(hipMalloc((void**)&d_ops, L.ops.size() * sizeof(FuseOpDev)));
+        TANQ_HIP(hipMalloc((void**)&d_blk, L.blocks.size() * sizeof(FuseBlockDev)));
+        TANQ_HIP(hipMalloc((void**)&d_kraus, L.kraus.size() * sizeof(double)));
+        TANQ_HIP(hipMalloc((void**)&d_sops, L.sop_elems * 2 * sizeof(double)));
+        TANQ_HIP(hipMalloc((void**)&f->raw, L.raw_elems * 2 * sizeof(double)));
+        TANQ_HIP(hipMalloc((void**)&f->packed, L.pack_bytes));
+        TANQ_HIP(hipMemcpyAsync(d_ops, L.ops.data(), L.ops.size() * sizeof(FuseOpDev), hipMemcpyHostToDevice, s));
+        TANQ_HIP(hipMemcpyAsync(d_blk, L.blocks.data(), L.blocks.size() * sizeof(FuseBlockDev), hipMemcpyHostToDevice, s));
+        TANQ_HIP(hipMemcpyAsync(d_kraus, L.kraus.data(), L.kraus.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        run_fuse_kernels(L, d_ops, d_blk, d_kraus, d_sops, f->raw, f->packed, p, s);
         TANQ_HIP(hipStreamSynchronize(s));
       } catch (...) {
         (void)hipStreamSynchronize(s);
@@ -544,12 +484,7 @@ tanq_status tanq_fuse_plan(tanq_circuit c, int max_width, int* op_block, int* nb
     if (!c || !nblocks) fail(TANQ_E_ARG, "NULL argument");
     if (max_width < -2 || max_width > 3 || max_width == 0) fail(TANQ_E_ARG, "max_width must be -2, -1, 1, 2 or 3");
     if (!c->ops.empty() && !op_block) fail(TANQ_E_ARG, "op_block is NULL");
-    std::vector<PlanOp> pops(c->ops.size());
-    for (size_t i = 0; i < c->ops.size(); ++i) {
-      pops[i].j = c->ops[i].j;
-      for (int t = 0; t < 3; ++t) pops[i].q[t] = c->ops[i].q[t];
-    }
-    const std::vector<PlanBlock> plan = plan_fusion(pops, c->n, max_width);
+    const std::vector<PlanBlock> plan = plan_fusion(plan_ops(c->ops), c->n, max_width);
     for (size_t b = 0; b < plan.size(); ++b)
       for (int oi : plan[b].ops) op_block[oi] = (int)b;
     *nblocks = (int)plan.size();
@@ -802,6 +737,21 @@ tanq_status tanq_expect_pauli_batch(tanq_dm d, int count, const char* const* pau
         if (out_im) out_im[base + i] = res[2 * i + 1];
       }
     }
+  });
+}
+
+tanq_status tanq_dm_compare(tanq_dm a, tanq_dm b, double* out3) {
+  return guarded([&] {
+    check_dm(a);
+    check_dm(b);
+    if (!out3) fail(TANQ_E_ARG, "out3 is NULL");
+    if (a->n != b->n) fail(TANQ_E_ARG, "different qubit counts");
+    if (a->device != b->device) fail(TANQ_E_ARG, "handles live on different devices");
+    DeviceGuard g(a->device);
+    TANQ_HIP(hipStreamSynchronize(b->stream));
+    launch_compare(a->ptr, a->prec, b->ptr, b->prec, a->elements(), a->partials, a->result_dev, a->stream);
+    TANQ_HIP(hipMemcpyAsync(out3, a->result_dev, 3 * sizeof(double), hipMemcpyDeviceToHost, a->stream));
+    TANQ_HIP(hipStreamSynchronize(a->stream));
   });
 }
 

@@ -41,6 +41,8 @@ struct ApplyGeom {
   uint64_t ntiles;        // number of tiles = 2^(2n - V)
   uint32_t tj[64];        // tile-local index of each superoperator local index l < 4^k
   uint32_t free_mask;     // tile-local bits that index groups inside the tile
+  uint32_t xsrc;          // LDS swizzle: group bits above the bank window ...
+  uint32_t xdst;          // ... copied (XOR) into these target-bit positions inside it
   int32_t V;              // tile bits
   int32_t G;              // groups per tile = 2^(V - 2k)
   int32_t nruns;          // runs of fixed bits
@@ -76,14 +78,31 @@ struct FuseBlockDev {
   int64_t pack_off;   // offset (elements of the packed precision) of the packed operand
 };
 
+// Serving: one batched launch applies one superoperator to each of many states.  Items and
+// chunks live in device memory; a chunk is a range of tiles of one item.
+struct BatchItem {
+  uint64_t rho;   // device address of the state
+  uint64_t frag;  // device address of the packed operand
+  ApplyGeom g;
+};
+
+struct BatchChunk {
+  uint32_t item;
+  uint32_t tile_begin;
+  uint32_t tile_end;
+  uint32_t pad;
+};
+
 // Packed operand sizes (elements of T) per superoperator width.
-constexpr int packed_elems(int k) { return k == 1 ? 32 : (k == 2 ? 32 * 32 : 128 * 128); }
+//   k = 1: 4x4 complex FP64 (32 doubles); k = 2: real-block 32 x 32; k = 3: 3M planar
+//   (Sr, Si, Sr + Si) as 4 m-tiles x 16 k-steps x 3 x 64 lanes.
+constexpr int packed_elems(int k) { return k == 1 ? 32 : (k == 2 ? 32 * 32 : 4 * 16 * 3 * 64); }
 
 // ------------------------------------------------------------------------------------
 // launchers (kernels.hip)
 // ------------------------------------------------------------------------------------
 
-ApplyGeom make_apply_geom(int n, int k, const int* qubits, int vbits);
+ApplyGeom make_apply_geom(int n, int k, const int* qubits, int vbits, tanq_prec p);
 
 // Apply-kernel variants per (k, precision), k in {2, 3}: count, shape, process-wide choice.
 int variant_count(int k, tanq_prec p);
@@ -121,6 +140,18 @@ void launch_diag(const void* rho, int n, tanq_prec p, double* probs_dev, double*
 void launch_pauli(const void* rho, int n, tanq_prec p, int count, const uint64_t* masks_dev,
                   double* partials, double* result_dev, hipStream_t s);
 
+// out3 = (||a-b||_F, max|a-b|, ||a||_F); partials: reduce_partials() doubles.
+void launch_compare(const void* a, tanq_prec pa, const void* b, tanq_prec pb, uint64_t nel, double* partials,
+                    double* result_dev, hipStream_t s);
+
 int device_cu_count();
+
+// Tile bits of the batched kernel for width k (2 or 3) and precision p (geometry of the items
+// must be built with this value).
+int batch_tile_bits(int k, tanq_prec p);
+// Apply the items of `*count` chunks (count lives in device memory so the launch can be
+// captured in a graph and replayed with new contents).
+void launch_batch(int k, tanq_prec p, const BatchItem* items, const BatchChunk* chunks, const uint32_t* count,
+                  hipStream_t s);
 
 }  // namespace tanq

@@ -37,11 +37,14 @@ EXPORTED = [
     "tanq_dm_init", "tanq_dm_wrap", "tanq_dm_free", "tanq_dm_reset", "tanq_dm_query",
     "tanq_dm_read", "tanq_dm_write", "tanq_dm_fill_random", "tanq_dm_gather", "tanq_sync",
     "tanq_circuit_create", "tanq_circuit_free", "tanq_circuit_add_gate", "tanq_circuit_add_kraus",
-    "tanq_circuit_size",
+    "tanq_circuit_add_ops", "tanq_circuit_size",
     "tanq_fuse", "tanq_fuse_plan", "tanq_fused_info", "tanq_fused_free", "tanq_fused_get",
     "tanq_apply_superop", "tanq_apply_fused", "tanq_apply_fused_range",
     "tanq_variant_count", "tanq_variant_get", "tanq_variant_select", "tanq_variant_selected", "tanq_autotune",
     "tanq_probs", "tanq_expect_pauli", "tanq_expect_pauli_c", "tanq_expect_pauli_batch",
+    "tanq_dm_compare",
+    "tanq_server_create", "tanq_server_submit", "tanq_server_poll", "tanq_server_wait", "tanq_server_release",
+    "tanq_server_stats_get", "tanq_server_destroy",
 ]
 
 
@@ -53,6 +56,29 @@ class TanqError(RuntimeError):
 
 class Variant(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int), ("prec", ctypes.c_int), ("tile_bits", ctypes.c_int), ("threads", ctypes.c_int)]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_slots", ctypes.c_int), ("prec", ctypes.c_int),
+                ("width", ctypes.c_int), ("steps_per_launch", ctypes.c_int), ("use_graphs", ctypes.c_int)]
+
+
+class Outputs(ctypes.Structure):
+    _fields_ = [("probs", ctypes.c_int), ("npauli", ctypes.c_int), ("paulis", ctypes.POINTER(ctypes.c_char_p))]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("n", ctypes.c_int), ("trace", ctypes.c_double),
+                ("probs", ctypes.POINTER(ctypes.c_double)), ("pauli", ctypes.POINTER(ctypes.c_double)),
+                ("npauli", ctypes.c_int), ("fused_applies", ctypes.c_int),
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("admitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("rejected", ctypes.c_uint64), ("launches", ctypes.c_uint64), ("steps", ctypes.c_uint64),
+                ("bytes_in_use", ctypes.c_size_t), ("peak_bytes", ctypes.c_size_t), ("budget_bytes", ctypes.c_size_t),
+                ("active", ctypes.c_int), ("pending", ctypes.c_int), ("clock", ctypes.c_double)]
 
 
 class FusedInfo(ctypes.Structure):
@@ -83,6 +109,8 @@ _SIGS = {
     "tanq_circuit_free": ([_vp], ctypes.c_int),
     "tanq_circuit_add_gate": ([_vp, ctypes.c_int, _ip, _dp], ctypes.c_int),
     "tanq_circuit_add_kraus": ([_vp, ctypes.c_int, _ip, ctypes.c_int, _dp], ctypes.c_int),
+    "tanq_circuit_add_ops": ([_vp, ctypes.c_int, _ip, _ip, _ip, ctypes.POINTER(ctypes.c_int64), _dp,
+                              ctypes.c_size_t], ctypes.c_int),
     "tanq_circuit_size": ([_vp, _ip], ctypes.c_int),
     "tanq_fuse": ([_vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.POINTER(_vp)], ctypes.c_int),
     "tanq_fuse_plan": ([_vp, ctypes.c_int, _ip, _ip], ctypes.c_int),
@@ -101,6 +129,14 @@ _SIGS = {
     "tanq_expect_pauli": ([_vp, ctypes.c_char_p, _dp], ctypes.c_int),
     "tanq_expect_pauli_c": ([_vp, ctypes.c_char_p, _dp, _dp], ctypes.c_int),
     "tanq_expect_pauli_batch": ([_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_char_p), _dp, _dp], ctypes.c_int),
+    "tanq_dm_compare": ([_vp, _vp, _dp], ctypes.c_int),
+    "tanq_server_create": ([ctypes.POINTER(ServerConfig), ctypes.POINTER(_vp)], ctypes.c_int),
+    "tanq_server_submit": ([_vp, _vp, ctypes.POINTER(Outputs), ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
+    "tanq_server_poll": ([_vp, ctypes.c_uint64, ctypes.POINTER(Result)], ctypes.c_int),
+    "tanq_server_wait": ([_vp, ctypes.c_uint64, ctypes.POINTER(Result)], ctypes.c_int),
+    "tanq_server_release": ([_vp, ctypes.c_uint64], ctypes.c_int),
+    "tanq_server_stats_get": ([_vp, ctypes.POINTER(ServerStats)], ctypes.c_int),
+    "tanq_server_destroy": ([_vp], ctypes.c_int),
 }
 
 
@@ -223,6 +259,17 @@ def tanq_circuit_add_kraus(h: int, qubits: Sequence[int], K: np.ndarray):
     _check(load().tanq_circuit_add_kraus(h, len(qubits), _ints(qubits), K.shape[0], p))
 
 
+def tanq_circuit_add_ops(h: int, j: np.ndarray, q: np.ndarray, m: np.ndarray, koff: np.ndarray, pool: np.ndarray):
+    j = np.ascontiguousarray(j, dtype=np.int32)
+    q = np.ascontiguousarray(q, dtype=np.int32).reshape(-1)
+    m = np.ascontiguousarray(m, dtype=np.int32)
+    koff = np.ascontiguousarray(koff, dtype=np.int64)
+    pool = np.ascontiguousarray(pool, dtype=np.float64)
+    _check(load().tanq_circuit_add_ops(h, int(j.size), j.ctypes.data_as(_ip), q.ctypes.data_as(_ip),
+                                       m.ctypes.data_as(_ip), koff.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                       pool.ctypes.data_as(_dp), pool.size))
+
+
 def tanq_circuit_size(h: int) -> int:
     c = ctypes.c_int()
     _check(load().tanq_circuit_size(h, ctypes.byref(c)))
@@ -339,6 +386,70 @@ def tanq_expect_pauli_batch(h: int, paulis: Sequence[str]) -> np.ndarray:
     return re + 1j * im
 
 
+def tanq_dm_compare(a: int, b: int):
+    """(||a-b||_F, max|a-b|, ||a||_F) computed on the GPU in FP64."""
+    out = (ctypes.c_double * 3)()
+    _check(load().tanq_dm_compare(a, b, out))
+    return tuple(out)
+
+
+def tanq_server_create(hbm_budget: int, max_slots: int, prec: int, width: int = 2,
+                       steps_per_launch: int = 8, use_graphs: bool = True) -> int:
+    cfg = ServerConfig(hbm_budget, max_slots, prec, width, steps_per_launch, int(bool(use_graphs)))
+    h = _vp()
+    _check(load().tanq_server_create(ctypes.byref(cfg), ctypes.byref(h)))
+    return h.value
+
+
+def tanq_server_submit(h: int, circuit: int, probs: bool = True, paulis: Sequence[str] = ()) -> int:
+    arr = (ctypes.c_char_p * max(len(paulis), 1))(*[p.encode() for p in paulis])
+    outs = Outputs(int(bool(probs)), len(paulis), arr)
+    t = ctypes.c_uint64()
+    _check(load().tanq_server_submit(h, circuit, ctypes.byref(outs), ctypes.byref(t)))
+    return t.value
+
+
+def _result_dict(r: Result) -> dict:
+    out = {"status": r.status, "n": r.n, "trace": r.trace, "fused_applies": r.fused_applies,
+           "t_submit": r.t_submit, "t_admit": r.t_admit, "t_done": r.t_done,
+           "probs": None, "pauli": None}
+    if r.probs:
+        out["probs"] = np.ctypeslib.as_array(r.probs, shape=(1 << r.n,)).copy()
+    if r.pauli and r.npauli:
+        out["pauli"] = np.ctypeslib.as_array(r.pauli, shape=(r.npauli,)).copy()
+    return out
+
+
+def tanq_server_poll(h: int, ticket: int):
+    """Result dict, or None while the request is not finished."""
+    r = Result()
+    rc = load().tanq_server_poll(h, ticket, ctypes.byref(r))
+    if rc == TANQ_E_AGAIN:
+        return None
+    _check(rc)
+    return _result_dict(r)
+
+
+def tanq_server_wait(h: int, ticket: int) -> dict:
+    r = Result()
+    _check(load().tanq_server_wait(h, ticket, ctypes.byref(r)))
+    return _result_dict(r)
+
+
+def tanq_server_release(h: int, ticket: int):
+    _check(load().tanq_server_release(h, ticket))
+
+
+def tanq_server_stats_get(h: int) -> dict:
+    st = ServerStats()
+    _check(load().tanq_server_stats_get(h, ctypes.byref(st)))
+    return {name: getattr(st, name) for name, _ in ServerStats._fields_}
+
+
+def tanq_server_destroy(h: int):
+    _check(load().tanq_server_destroy(h))
+
+
 # ---------------------------------------------------------------------------------------
 # handle wrappers
 # ---------------------------------------------------------------------------------------
@@ -412,6 +523,9 @@ class DM:
     def probs(self, renormalize: bool = True):
         return tanq_probs(self.h, 1 << self.n, renormalize)
 
+    def compare(self, other: "DM"):
+        return tanq_dm_compare(self.h, other.h)
+
     def autotune(self, reps: int = 3) -> list:
         return tanq_autotune(self.h, reps)
 
@@ -423,11 +537,17 @@ class DM:
 
 
 class Circuit:
-    def __init__(self, n: int, ops: Iterable = ()):
+    def __init__(self, n: int, ops: Iterable = (), arrays=None):
         self.n = n
         self.h = tanq_circuit_create(n)
+        if arrays is not None:
+            self.add_arrays(arrays)
         for op in ops:
             self.add(op)
+
+    def add_arrays(self, ca):
+        """Append a pooled circuit (workloads.CircuitArrays) in one call."""
+        tanq_circuit_add_ops(self.h, ca.j, ca.q, ca.m, ca.koff, ca.pool)
 
     def add(self, op):
         if op.mats.shape[0] == 1 and op.kind == "gate":
@@ -491,3 +611,47 @@ def simulate(n: int, ops: Iterable, max_width: int = TANQ_FUSE_AUTO, prec="f64",
     f.free()
     c.free()
     return d
+
+
+class Server:
+    """Continuous-batching server (see tanq_server_* in include/tanq.h)."""
+
+    def __init__(self, hbm_budget: int, max_slots: int = 64, prec="f32", width: int = 2,
+                 steps_per_launch: int = 8, use_graphs: bool = True):
+        self.h = tanq_server_create(hbm_budget, max_slots, _prec(prec), width, steps_per_launch, use_graphs)
+
+    def submit(self, n: int, ops: Iterable = (), probs: bool = True, paulis: Sequence[str] = (), arrays=None) -> int:
+        c = Circuit(n, ops, arrays=arrays)
+        try:
+            return tanq_server_submit(self.h, c.h, probs, paulis)
+        finally:
+            c.free()
+
+    def poll(self, ticket: int):
+        return tanq_server_poll(self.h, ticket)
+
+    def wait(self, ticket: int) -> dict:
+        return tanq_server_wait(self.h, ticket)
+
+    def release(self, ticket: int):
+        tanq_server_release(self.h, ticket)
+
+    def stats(self) -> dict:
+        return tanq_server_stats_get(self.h)
+
+    def close(self):
+        if self.h:
+            tanq_server_destroy(self.h)
+            self.h = 0
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

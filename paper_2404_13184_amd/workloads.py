@@ -401,19 +401,177 @@ def config5(num_requests: int = 5000, rate_hz: float = 200.0, seed: int = 5,
     return out
 
 
-def request_ops(req: Request, seed_base: int = 1000) -> List[Op]:
-    seed = seed_base + req.rid
+# --------------------------------------------------------------------------------------
+# Pooled array form (for large request streams): one matrix pool per circuit plus, per
+# operation, its width j, qubits (padded to 3), Kraus count m and offset into the pool
+# (in doubles).  Repeated channels point at one copy.
+# --------------------------------------------------------------------------------------
+
+
+@dataclasses.dataclass
+class CircuitArrays:
+    n: int
+    j: np.ndarray       # int32 [count]
+    q: np.ndarray       # int32 [count, 3]
+    m: np.ndarray       # int32 [count]
+    koff: np.ndarray    # int64 [count]
+    pool: np.ndarray    # float64, interleaved complex matrices
+    labels: List[str]
+
+    @property
+    def count(self) -> int:
+        return int(self.j.size)
+
+
+class _PoolBuilder:
+    def __init__(self):
+        self.chunks: List[np.ndarray] = []
+        self.size = 0
+
+    def add(self, mats: np.ndarray) -> int:
+        """Append matrices (complex, any leading shape); returns their offset in doubles."""
+        a = np.ascontiguousarray(mats, dtype=np.complex128).view(np.float64).reshape(-1)
+        off = self.size
+        self.chunks.append(a)
+        self.size += a.size
+        return off
+
+    def pool(self) -> np.ndarray:
+        return np.concatenate(self.chunks) if self.chunks else np.zeros(0)
+
+
+def u3_batch(theta: np.ndarray, phi: np.ndarray, lam: np.ndarray) -> np.ndarray:
+    """U3 for arrays of angles: shape (..., 2, 2)."""
+    c, s_ = np.cos(theta / 2), np.sin(theta / 2)
+    out = np.empty(theta.shape + (2, 2), dtype=np.complex128)
+    out[..., 0, 0] = c
+    out[..., 0, 1] = -np.exp(1j * lam) * s_
+    out[..., 1, 0] = np.exp(1j * phi) * s_
+    out[..., 1, 1] = np.exp(1j * (phi + lam)) * c
+    return out
+
+
+class _OpRecorder:
+    def __init__(self, n):
+        self.n = n
+        self.j, self.q, self.m, self.koff, self.labels = [], [], [], [], []
+
+    def op(self, qubits, m, koff, label):
+        self.j.append(len(qubits))
+        self.q.append(tuple(qubits) + (0,) * (3 - len(qubits)))
+        self.m.append(m)
+        self.koff.append(koff)
+        self.labels.append(label)
+
+    def finish(self, pb: _PoolBuilder) -> CircuitArrays:
+        return CircuitArrays(self.n, np.asarray(self.j, dtype=np.int32),
+                             np.asarray(self.q, dtype=np.int32).reshape(-1, 3),
+                             np.asarray(self.m, dtype=np.int32), np.asarray(self.koff, dtype=np.int64),
+                             pb.pool(), self.labels)
+
+
+def request_arrays(req: Request, seed_base: int = 1000) -> CircuitArrays:
+    """The request's circuit in pooled array form (the definition of its operations).
+
+    Types: "u3cx" (layers of U3 + dep(p1) on every qubit, CX on a random disjoint pairing +
+    dep2(p2)), "ising" (Trotter steps as in :func:`ising_trotter`, thermal relaxation with
+    T1 = T2 = 0.05 / p1 and gate time 0.05 after every gate), "teleport" (layers of teleport
+    blocks on a random disjoint set of triples, as in :func:`teleport_block`).
+    """
+    rng = np.random.default_rng(seed_base + req.rid)
+    n = req.n
     p1, p2 = req.p1, min(10 * req.p1, 0.5)
+    pb, rec = _PoolBuilder(), _OpRecorder(n)
+    two_pi = 2 * math.pi
     if req.kind == "u3cx":
-        return random_u3_cx(req.n, req.depth, seed, p1, p2)
-    if req.kind == "ising":
-        # thermal relaxation scaled so the per-gate error is of order p1
+        d1 = pb.add(np.stack(depolarizing(p1, 1)))
+        d2 = pb.add(np.stack(depolarizing(p2, 2)))
+        cxo = pb.add(cx())
+        for _ in range(req.depth):
+            ang = rng.uniform(0.0, two_pi, size=(n, 3))
+            uo = pb.add(u3_batch(ang[:, 0], ang[:, 1], ang[:, 2]))
+            for qq in range(n):
+                rec.op((qq,), 1, uo + 8 * qq, "u3")
+                rec.op((qq,), 4, d1, "dep1")
+            perm = rng.permutation(n)
+            for i in range(n // 2):
+                c, t = int(perm[2 * i]), int(perm[2 * i + 1])
+                rec.op((c, t), 1, cxo, "cx")
+                rec.op((c, t), 16, d2, "dep2")
+    elif req.kind == "ising":
+        dt, J = 0.05, 1.0
+        h = rng.uniform(0.5, 1.5, size=n)
         t1 = 0.05 / p1
-        ops, _ = ising_trotter(req.n, req.depth, seed, t1=t1, t2=t1, tg=0.05)
-        return ops
-    if req.kind == "teleport":
-        return teleport_layers(req.n, req.depth, seed, p1, p2)
-    raise ValueError(req.kind)
+        tr = thermal_relaxation(t1, t1, 0.05)
+        tro = pb.add(np.stack(tr))
+        rzo = pb.add(rzz(2 * J * dt))
+        rxo = pb.add(np.stack([rx(2 * h[qq] * dt) for qq in range(n)]))
+        for _ in range(req.depth):
+            for a in range(n - 1):
+                rec.op((a, a + 1), 1, rzo, "rzz")
+                rec.op((a,), len(tr), tro, "tr")
+                rec.op((a + 1,), len(tr), tro, "tr")
+            for qq in range(n):
+                rec.op((qq,), 1, rxo + 8 * qq, "rx")
+                rec.op((qq,), len(tr), tro, "tr")
+    elif req.kind == "teleport":
+        d1 = pb.add(np.stack(depolarizing(p1, 1)))
+        d2 = pb.add(np.stack(depolarizing(p2, 2)))
+        ho, cxo, czo = pb.add(hadamard()), pb.add(cx()), pb.add(cz())
+        meo = pb.add(np.stack(dephase()))
+        for _ in range(req.depth):
+            perm = rng.permutation(n)
+            ang = rng.uniform(0.0, two_pi, size=(n // 3, 3))
+            uo = pb.add(u3_batch(ang[:, 0], ang[:, 1], ang[:, 2]))
+            for i in range(n // 3):
+                a, b, c = (int(x) for x in perm[3 * i:3 * i + 3])
+                rec.op((a,), 1, uo + 8 * i, "u3")
+                rec.op((a,), 4, d1, "dep1")
+                rec.op((b,), 1, ho, "h")
+                rec.op((b,), 4, d1, "dep1")
+                rec.op((b, c), 1, cxo, "cx")
+                rec.op((b, c), 16, d2, "dep2")
+                rec.op((a, b), 1, cxo, "cx")
+                rec.op((a, b), 16, d2, "dep2")
+                rec.op((a,), 1, ho, "h")
+                rec.op((a,), 4, d1, "dep1")
+                rec.op((a,), 2, meo, "meas")
+                rec.op((b,), 2, meo, "meas")
+                rec.op((b, c), 1, cxo, "cx")
+                rec.op((b, c), 16, d2, "dep2")
+                rec.op((a, c), 1, czo, "cz")
+                rec.op((a, c), 16, d2, "dep2")
+    else:
+        raise ValueError(req.kind)
+    return rec.finish(pb)
+
+
+def arrays_to_ops(ca: CircuitArrays) -> List[Op]:
+    """Expand the pooled form into explicit :class:`Op` records."""
+    ops = []
+    for i in range(ca.count):
+        j, m, off = int(ca.j[i]), int(ca.m[i]), int(ca.koff[i])
+        d = 1 << j
+        mats = ca.pool[off:off + m * d * d * 2].view(np.complex128).reshape(m, d, d).copy()
+        qs = tuple(int(x) for x in ca.q[i, :j])
+        ops.append(Op("gate" if m == 1 else "kraus", qs, mats, ca.labels[i]))
+    return ops
+
+
+def ops_to_arrays(n: int, ops: Sequence[Op]) -> CircuitArrays:
+    """Pooled form of an explicit operation list (matrices deduplicated by identity)."""
+    pb, rec = _PoolBuilder(), _OpRecorder(n)
+    seen = {}
+    for op in ops:
+        key = id(op.mats)
+        if key not in seen:
+            seen[key] = pb.add(op.mats)
+        rec.op(op.qubits, op.mats.shape[0], seen[key], op.label)
+    return rec.finish(pb)
+
+
+def request_ops(req: Request, seed_base: int = 1000) -> List[Op]:
+    return arrays_to_ops(request_arrays(req, seed_base))
 
 
 def zz_paulis(n: int) -> List[str]:

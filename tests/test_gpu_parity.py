@@ -344,3 +344,19 @@ def test_error_paths_on_device():
         with pytest.raises(T.TanqError):
             d.apply_fused(f2)
         f2.free()
+
+
+@pytest.mark.parametrize("pa,pb", [("f64", "f64"), ("f32", "f64"), ("f64", "f32")])
+def test_dm_compare(oracle_mod, pa, pb):
+    rng = np.random.default_rng(123)
+    n = 6
+    ra, rb = random_density(rng, n), random_density(rng, n)
+    say("compare %s %s" % (pa, pb))
+    with T.DM(n, pa) as a, T.DM(n, pb) as b:
+        a.write(oracle_mod.matrix_to_vec(ra))
+        b.write(oracle_mod.matrix_to_vec(rb))
+        fro, mx, nrm = a.compare(b)
+        va, vb = a.read().astype(np.complex128), b.read().astype(np.complex128)
+    assert abs(fro - np.linalg.norm(va - vb)) <= 1e-12 * np.linalg.norm(va - vb)
+    assert abs(mx - np.abs(va - vb).max()) <= 1e-15
+    assert abs(nrm - np.linalg.norm(va)) <= 1e-12 * np.linalg.norm(va)

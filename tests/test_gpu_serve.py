@@ -1,0 +1,122 @@
+"""Continuous-batching server on the GPU: results against the oracle, identical alone and in a
+mix, admission within the device-memory budget, rejection of requests that can never fit."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2404_13184_amd import tanq as T
+from paper_2404_13184_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+MiB = 1 << 20
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def small_requests(count, seed, n_range=(4, 7), depth_range=(2, 6)):
+    reqs = W.config5(num_requests=count, seed=seed, n_range=n_range, depth_range=depth_range)
+    return [(r.n, W.request_ops(r), r) for r in reqs]
+
+
+@pytest.mark.parametrize("prec,width", [("f64", 2), ("f64", 3), ("f32", 2), ("f32", 3)])
+def test_server_results_match_oracle(oracle_mod, prec, width):
+    reqs = small_requests(12, seed=50 + width)
+    say("server parity %s width %d" % (prec, width))
+    with T.Server(256 * MiB, max_slots=8, prec=prec, width=width, steps_per_launch=4) as srv:
+        tickets = []
+        for n, ops, _ in reqs:
+            tickets.append(srv.submit(n, ops, probs=True, paulis=W.zz_paulis(n)[:2] + W.z_paulis(n)[:1]))
+        for (n, ops, _), t in zip(reqs, tickets):
+            res = srv.wait(t)
+            assert res["status"] == T.TANQ_OK
+            want = oracle_mod.run(n, ops)
+            p, tr = oracle_mod.diag(want)
+            tol = 1e-12 if prec == "f64" else 1e-5
+            assert abs(res["trace"] - tr) <= tol
+            assert np.abs(res["probs"] - p / tr).max() <= tol
+            strings = W.zz_paulis(n)[:2] + W.z_paulis(n)[:1]
+            for s, v in zip(strings, res["pauli"]):
+                assert abs(v - oracle_mod.expect_pauli(want, s).real) <= (1e-12 if prec == "f64" else 1e-5)
+            srv.release(t)
+        st = srv.stats()
+        assert st["completed"] == len(reqs) and st["bytes_in_use"] == 0
+
+
+@pytest.mark.parametrize("use_graphs", [True, False])
+def test_alone_equals_in_mix(use_graphs):
+    reqs = small_requests(24, seed=77, n_range=(4, 9), depth_range=(3, 12))
+    target = reqs[5]
+    say("alone vs mix, graphs=%s" % use_graphs)
+    with T.Server(512 * MiB, max_slots=16, prec="f32", width=2, steps_per_launch=8, use_graphs=use_graphs) as srv:
+        t = srv.submit(target[0], target[1], probs=True, paulis=W.z_paulis(target[0]))
+        alone = srv.wait(t)
+    with T.Server(512 * MiB, max_slots=16, prec="f32", width=2, steps_per_launch=8, use_graphs=use_graphs) as srv:
+        tickets = [srv.submit(n, ops, probs=True, paulis=W.z_paulis(n)) for n, ops, _ in reqs]
+        mixed = [srv.wait(t) for t in tickets]
+    got = mixed[5]
+    assert got["status"] == T.TANQ_OK and alone["status"] == T.TANQ_OK
+    assert np.array_equal(got["probs"], alone["probs"])  # bitwise
+    assert np.array_equal(got["pauli"], alone["pauli"])
+    assert got["trace"] == alone["trace"]
+
+
+def test_graph_and_direct_launches_agree():
+    reqs = small_requests(10, seed=31, n_range=(5, 8), depth_range=(4, 8))
+    say("graph vs direct")
+    outs = []
+    for g in (True, False):
+        with T.Server(256 * MiB, max_slots=4, prec="f32", width=3, steps_per_launch=3, use_graphs=g) as srv:
+            tickets = [srv.submit(n, ops) for n, ops, _ in reqs]
+            outs.append([srv.wait(t)["probs"] for t in tickets])
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+
+
+def test_admission_respects_budget():
+    # each 9-qubit FP32 request holds 2 MiB of state plus its operands; a 64 MiB budget admits a few
+    reqs = small_requests(40, seed=8, n_range=(9, 9), depth_range=(5, 10))
+    say("admission budget")
+    with T.Server(64 * MiB, max_slots=64, prec="f32", width=2, steps_per_launch=4) as srv:
+        tickets = [srv.submit(n, ops) for n, ops, _ in reqs]
+        res = [srv.wait(t) for t in tickets]
+        st = srv.stats()
+    assert all(r["status"] == T.TANQ_OK for r in res)
+    assert st["peak_bytes"] <= st["budget_bytes"]
+    assert st["completed"] == len(reqs)
+    assert all(abs(r["trace"] - 1.0) <= 1e-5 for r in res)
+    # FIFO admission: admit times do not decrease with submission order
+    admits = [r["t_admit"] for r in res]
+    assert all(b >= a for a, b in zip(admits, admits[1:]))
+
+
+def test_rejects_requests_that_never_fit():
+    with T.Server(64 * MiB, max_slots=4, prec="f64", width=2) as srv:
+        n = 12  # FP64 state alone is 256 MiB
+        with pytest.raises(T.TanqError) as e:
+            srv.submit(n, W.random_u3_cx(n, 1, seed=1, p1=1e-3, p2=1e-2))
+        assert e.value.code == T.TANQ_E_OOM
+        with pytest.raises(T.TanqError) as e:
+            srv.submit(1, [W.gate(W.hadamard(), (0,))])  # narrower than the fusion width
+        assert e.value.code == T.TANQ_E_ARG
+        assert srv.stats()["rejected"] == 1
+
+
+def test_arrivals_while_busy_overlap():
+    """Requests submitted while others are resident join the running batch."""
+    reqs = small_requests(16, seed=12, n_range=(8, 10), depth_range=(20, 30))
+    say("arrivals while busy")
+    with T.Server(1024 * MiB, max_slots=16, prec="f32", width=2, steps_per_launch=4) as srv:
+        first = [srv.submit(n, ops) for n, ops, _ in reqs[:8]]
+        import time
+        time.sleep(0.002)
+        second = [srv.submit(n, ops) for n, ops, _ in reqs[8:]]
+        res = [srv.wait(t) for t in first + second]
+    assert all(r["status"] == T.TANQ_OK for r in res)
+    # some request of the second wave was admitted before the last of the first wave finished
+    last_first_done = max(r["t_done"] for r in res[:8])
+    assert min(r["t_admit"] for r in res[8:]) < last_first_done
