@@ -39,6 +39,12 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=12)
     ap.add_argument("--cpu-budget-s", type=float, default=20.0)
+    ap.add_argument("--serve-requests", type=int, default=5000, help="0 skips the serving stream")
+    ap.add_argument("--serve-width", type=int, default=2)
+    ap.add_argument("--serve-slots", type=int, default=64)
+    ap.add_argument("--serve-steps", type=int, default=8)
+    ap.add_argument("--serve-budget-gb", type=float, default=32.0)
+    ap.add_argument("--plain-budget-s", type=float, default=30.0)
     return ap.parse_args()
 
 
@@ -143,6 +149,95 @@ def cpu_baseline(W, n_full, layers_full, cpu_n, budget_s):
             "cores": oracle.max_threads(), "cpu_n": cpu_n}
 
 
+def _gen_arrays(args):
+    from paper_2404_13184_amd import workloads as W
+
+    return W.request_arrays(args)
+
+
+def serving_requests(W, num, seed=5):
+    """The request stream and each request's circuit (pooled arrays), generated in parallel."""
+    import multiprocessing as mp
+
+    reqs = W.config5(num_requests=num, seed=seed)
+    workers = max(1, min(16, (os.cpu_count() or 2) - 1))
+    with mp.get_context("fork").Pool(workers) as pool:
+        arrays = pool.map(_gen_arrays, reqs, chunksize=32)
+    return reqs, arrays
+
+
+def _latency_summary(lat, done, first_arrival, last_done):
+    import numpy as np
+
+    lat = np.asarray(lat)
+    span = max(1e-9, last_done - first_arrival)
+    return {"completed": int(done), "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2) if lat.size else None,
+            "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2) if lat.size else None,
+            "mean_ms": round(float(lat.mean()) * 1e3, 2) if lat.size else None,
+            "circuits_per_s": round(done / span, 2)}
+
+
+def serve_batched(T, W, reqs, arrays, prec, width, budget, slots, steps):
+    """Open-loop replay of the stream through the continuous-batching server."""
+    srv = T.Server(budget, slots, prec, width, steps, use_graphs=True)
+    outs = {}
+    t0 = time.perf_counter()
+    c0 = srv.stats()["clock"]
+    tickets = []
+    for r, ca in zip(reqs, arrays):
+        dt = r.arrival_s - (time.perf_counter() - t0)
+        if dt > 0:
+            time.sleep(dt)
+        tickets.append(srv.submit(r.n, arrays=ca, probs=True, paulis=W.z_paulis(r.n)[:1]))
+    lat, last = [], 0.0
+    for r, t in zip(reqs, tickets):
+        res = srv.wait(t)
+        if res["status"] != 0:
+            raise RuntimeError("request %d failed: %d" % (r.rid, res["status"]))
+        done = res["t_done"] - c0
+        lat.append(done - r.arrival_s)
+        last = max(last, done)
+        outs[r.rid] = res["trace"]
+        srv.release(t)
+    st = srv.stats()
+    srv.close()
+    out = _latency_summary(lat, len(lat), reqs[0].arrival_s, last)
+    out.update({"peak_device_bytes": int(st["peak_bytes"]), "budget_bytes": int(st["budget_bytes"]),
+                "batched_applies": int(st["steps"]), "graph_launches": int(st["launches"]),
+                "wall_s": round(time.perf_counter() - t0, 2)})
+    return out
+
+
+def serve_plain(T, W, reqs, arrays, time_budget_s):
+    """The unbatched baseline: one request at a time in arrival order, FP64, one superoperator
+    per operation (no fusion).  Stops admitting new work after time_budget_s."""
+    lat = []
+    t0 = time.perf_counter()
+    last = 0.0
+    for r, ca in zip(reqs, arrays):
+        now = time.perf_counter() - t0
+        if now > time_budget_s:
+            break
+        if r.arrival_s > now:
+            time.sleep(r.arrival_s - now)
+        c = T.Circuit(r.n, arrays=ca)
+        f = c.fuse(T.TANQ_FUSE_NONE, "f64")
+        d = T.DM(r.n, "f64")
+        d.apply_fused(f)
+        d.probs(renormalize=True)
+        d.expect_pauli(W.z_paulis(r.n)[0])
+        d.free()
+        f.free()
+        c.free()
+        done = time.perf_counter() - t0
+        lat.append(done - r.arrival_s)
+        last = done
+    out = _latency_summary(lat, len(lat), reqs[0].arrival_s, last)
+    out["arrived_in_window"] = int(sum(1 for r in reqs if r.arrival_s <= last))
+    out["wall_s"] = round(time.perf_counter() - t0, 2)
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -214,6 +309,21 @@ def main():
                      "variants": rr["variants"]}
     if accuracy is not None:
         out["f32_vs_f64"] = accuracy
+    if a.serve_requests > 0:
+        log("serving: generating %d requests ..." % a.serve_requests)
+        reqs, arrays = serving_requests(W, a.serve_requests)
+        log("serving: FP32 continuous batching ...")
+        batched = serve_batched(T, W, reqs, arrays, "f32", a.serve_width, int(a.serve_budget_gb * (1 << 30)),
+                                a.serve_slots, a.serve_steps)
+        log("serving batched: %s" % batched)
+        log("serving: plain FP64 per request ...")
+        plain = serve_plain(T, W, reqs, arrays, a.plain_budget_s)
+        log("serving plain: %s" % plain)
+        out["serving"] = {"workload": "%d requests, Poisson 200/s, n ~ U{4..12}, depth ~ U{20..200}, "
+                                      "U3/CX, Ising Trotter and teleport blocks" % a.serve_requests,
+                          "batched_f32": dict(batched, width=a.serve_width, slots=a.serve_slots,
+                                              steps_per_launch=a.serve_steps),
+                          "plain_f64": plain}
     if not a.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         cb = cpu_baseline(W, n, a.layers, a.cpu_n, a.cpu_budget_s)

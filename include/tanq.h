@@ -223,6 +223,40 @@ tanq_status tanq_autotune(tanq_dm d, int reps, double* ms_per_apply);
  * trace.  Synchronises. */
 tanq_status tanq_probs(tanq_dm d, double* host_out, int renormalize, double* trace_out);
 
+/* Z-basis probabilities seen through a classical readout-error model (Sec. 3.5, measurement
+ * error): qubit t is read as 0 when it is 1 with probability p01[t] (P(0|1)) and as 1 when it
+ * is 0 with p10[t] (P(1|0)), independently, i.e. q = (x)_t [[1 - p10, p01], [p10, 1 - p01]] p
+ * with p the renormalised probabilities.  The paper's averaged model is p01 = p10.  FP64 on
+ * the GPU; host_out receives 2^n doubles.  Synchronises. */
+tanq_status tanq_probs_readout(tanq_dm d, const double* p01, const double* p10, double* host_out);
+
+/* Measure all qubits `shots` times (the all-measure operation): outcome i is the smallest x
+ * with cdf(x) > u_i * cdf(2^n - 1), cdf the FP64 prefix sums of the probabilities (after the
+ * readout model when p01/p10 are given, else both NULL) and u_i the top 53 bits of
+ * SplitMix64((seed << 40) + i) scaled to [0, 1).  host_out receives shots outcomes (bit t of an
+ * outcome = qubit t).  seed < 2^23.  Synchronises. */
+tanq_status tanq_sample(tanq_dm d, uint64_t shots, uint64_t seed, const double* p01, const double* p10,
+                        uint64_t* host_out);
+
+/* rho = |r><c| (a basis operator; not a state unless r == c).  Input of process tomography,
+ * where the channel is linear in its input.  Stream-ordered. */
+tanq_status tanq_dm_set_basis(tanq_dm d, uint64_t r, uint64_t c);
+
+/* Reduced density matrix on k <= 4 qubits keep[0..k-1] (keep[0] = least significant bit of
+ * the result's index): out[a][b] = sum_f rho[a|f][b|f] over the other qubits' values f.  FP64
+ * reduction on the GPU; host_out receives 4^k complex values (row-major, interleaved).
+ * Synchronises. */
+tanq_status tanq_reduced_dm(tanq_dm d, int k, const int* keep, double* host_out);
+
+/* Process tomography of a one-qubit channel defined by a circuit (Sec. 5, teleportation case
+ * study): for each basis operator |a><b| placed on in_qubit (every other qubit |0><0|), fuse
+ * and simulate the circuit on the GPU, reduce to out_qubit, and assemble the channel's 4 x 4
+ * superoperator S (column a + 2b = vec of the output).  chi_out receives the process matrix in
+ * the Pauli basis (I, X, Y, Z), E(rho) = sum_ij chi_ij sigma_i rho sigma_j, as 4 x 4 complex
+ * row-major; superop_out (may be NULL) receives S.  Synchronises. */
+tanq_status tanq_process_chi_1q(tanq_circuit c, int max_width, tanq_prec p, int in_qubit, int out_qubit,
+                                double* chi_out, double* superop_out);
+
 /* Re Tr(P rho) for the Pauli string P = (x)_t sigma_{pauli[t]}, pauli = n characters of
  * "IXYZ", character t acting on qubit t.  FP64 reduction.  Synchronises. */
 tanq_status tanq_expect_pauli(tanq_dm d, const char* pauli, double* out);

@@ -17,4 +17,9 @@ from .oracle import (  # noqa: F401
     trace_distance,
     vec_to_matrix,
     matrix_to_vec,
+    readout_probs,
+    sample,
+    splitmix64,
+    reduced_dm,
+    process_chi_1q,
 )

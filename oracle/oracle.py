@@ -9,6 +9,10 @@ Functions:
   the probabilities of every measurement outcome).
 * :func:`statevector` -- a plain state-vector simulator for circuits made only of unitary
   gates; for those circuits rho_out = |psi><psi| (the pure-state case of Sec. 2.1).
+* :func:`readout_probs`, :func:`sample` -- measurement through readout errors and sampled
+  outcomes (Sec. 3.5).
+* :func:`reduced_dm`, :func:`process_chi_1q` -- partial trace and single-qubit process
+  tomography of a circuit (Sec. 5, teleportation case study: the chi matrix).
 * :func:`trace_distance`, :func:`vec_to_matrix`, :func:`matrix_to_vec` -- comparison
   helpers; vec() is column stacking (Sec. 3.1): rho[r, c] sits at index r + c 2^n.
 
@@ -206,3 +210,91 @@ def sample_block(vec_in_values, n: int, ops: Sequence, row_free: int, col_free: 
 
     M_out = run(k, [_L(op) for op in ops], rho_in=M_in)
     return Q, M_in, M_out
+
+
+# --------------------------------------------------------------------------------------
+# measurement with readout error, and sampling (Sec. 3.5, measurement error)
+# --------------------------------------------------------------------------------------
+
+def splitmix64(x):
+    """SplitMix64 output for counter value(s) x (Steele, Lea & Flood, OOPSLA 2014): the state
+    advanced once by the golden gamma 0x9E3779B97F4A7C15, then the variant-13 finaliser."""
+    x = np.asarray(x, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = x + np.uint64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        return z ^ (z >> np.uint64(31))
+
+
+def readout_probs(p: np.ndarray, p01, p10) -> np.ndarray:
+    """Probabilities seen through independent per-qubit readout errors: qubit t is read as 0
+    when it is 1 with probability p01[t] and as 1 when it is 0 with p10[t].  Definition: the
+    confusion matrix (x)_t A_t, A_t = [[1 - p10, p01], [p10, 1 - p01]] (qubit t = bit t, the
+    right-most Kronecker factor first), applied to p."""
+    n = len(p01)
+    M = np.array([[1.0]])
+    for t in range(n):
+        A = np.array([[1.0 - p10[t], p01[t]], [p10[t], 1.0 - p01[t]]])
+        M = np.kron(A, M)
+    return M @ np.asarray(p, dtype=np.float64)
+
+
+def sample(p: np.ndarray, shots: int, seed: int) -> np.ndarray:
+    """All-qubit measurement outcomes: outcome i is the smallest x with cdf(x) > u_i cdf(end),
+    u_i = top 53 bits of SplitMix64((seed << 40) + i) / 2^53, cdf the prefix sums of p."""
+    cdf = np.cumsum(np.asarray(p, dtype=np.float64))
+    u = (splitmix64((np.uint64(seed) << np.uint64(40)) + np.arange(shots, dtype=np.uint64)) >> np.uint64(11))
+    u = u.astype(np.float64) * (2.0 ** -53) * cdf[-1]
+    return np.searchsorted(cdf, u, side="right").astype(np.uint64), u, cdf
+
+
+# --------------------------------------------------------------------------------------
+# partial trace and process tomography (Sec. 5, case study 1)
+# --------------------------------------------------------------------------------------
+
+_PAULI = (np.eye(2, dtype=np.complex128),
+          np.array([[0, 1], [1, 0]], dtype=np.complex128),
+          np.array([[0, -1j], [1j, 0]], dtype=np.complex128),
+          np.array([[1, 0], [0, -1]], dtype=np.complex128))
+
+
+def reduced_dm(rho: np.ndarray, keep: Sequence[int]) -> np.ndarray:
+    """Partial trace over every qubit not in ``keep``: out[a, b] = sum_f rho[a|f, b|f], where
+    bit t of a and b is qubit keep[t] and f runs over the values of the other qubits."""
+    dim = rho.shape[0]
+    n = dim.bit_length() - 1
+    keep = list(keep)
+    others = [q for q in range(n) if q not in keep]
+    k = len(keep)
+    out = np.zeros((1 << k, 1 << k), dtype=np.complex128)
+    dep_k = np.array([sum(((a >> t) & 1) << keep[t] for t in range(k)) for a in range(1 << k)], dtype=np.int64)
+    dep_f = np.array([sum(((f >> t) & 1) << others[t] for t in range(len(others)))
+                      for f in range(1 << len(others))], dtype=np.int64)
+    for a in range(1 << k):
+        for b in range(1 << k):
+            out[a, b] = rho[dep_k[a] + dep_f, dep_k[b] + dep_f].sum()
+    return out
+
+
+def process_chi_1q(n: int, ops: Iterable, src: int, dst: int) -> np.ndarray:
+    """chi of the channel that carries qubit ``src`` to qubit ``dst`` (every other qubit
+    starting in |0>), in the Pauli basis I, X, Y, Z: E(rho) = sum_ij chi_ij sigma_i rho sigma_j.
+
+    Standard process tomography: E is linear, so the outputs E(|a><b|) for the four basis
+    operators fix it; chi is the solution of the 16 linear equations
+    E(|a><b|)[r, c] = sum_ij chi_ij (sigma_i |a><b| sigma_j)[r, c]."""
+    ops = list(ops)
+    rows, rhs = [], []
+    for a in range(2):
+        for b in range(2):
+            E_ab = np.zeros((2, 2), dtype=np.complex128)
+            E_ab[a, b] = 1.0
+            rho_in = np.zeros((1 << n, 1 << n), dtype=np.complex128)
+            rho_in[a << src, b << src] = 1.0
+            out = reduced_dm(run(n, ops, rho_in), [dst])
+            for r in range(2):
+                for c in range(2):
+                    rows.append([(_PAULI[i] @ E_ab @ _PAULI[j])[r, c] for i in range(4) for j in range(4)])
+                    rhs.append(out[r, c])
+    return np.linalg.solve(np.array(rows), np.array(rhs)).reshape(4, 4)

@@ -714,6 +714,159 @@ tanq_status tanq_probs(tanq_dm d, double* host_out, int renormalize, double* tra
   });
 }
 
+static void check_readout(int n, const double* p01, const double* p10) {
+  if ((p01 == nullptr) != (p10 == nullptr)) fail(TANQ_E_ARG, "give both readout arrays or neither");
+  if (!p01) return;
+  for (int t = 0; t < n; ++t)
+    if (!(p01[t] >= 0.0 && p01[t] <= 1.0 && p10[t] >= 0.0 && p10[t] <= 1.0))
+      fail(TANQ_E_ARG, "readout error probabilities must be in [0, 1]");
+}
+
+tanq_status tanq_probs_readout(tanq_dm d, const double* p01, const double* p10, double* host_out) {
+  return guarded([&] {
+    check_dm(d);
+    if (!host_out || !p01 || !p10) fail(TANQ_E_ARG, "NULL argument");
+    check_readout(d->n, p01, p10);
+    DeviceGuard g(d->device);
+    launch_diag(d->ptr, d->n, d->prec, d->probs_dev, d->partials, d->result_dev, 1, d->stream);
+    launch_readout(d->probs_dev, d->n, p01, p10, d->stream);
+    TANQ_HIP(hipMemcpyAsync(host_out, d->probs_dev, (1ull << d->n) * sizeof(double), hipMemcpyDeviceToHost,
+                            d->stream));
+    TANQ_HIP(hipStreamSynchronize(d->stream));
+  });
+}
+
+tanq_status tanq_sample(tanq_dm d, uint64_t shots, uint64_t seed, const double* p01, const double* p10,
+                        uint64_t* host_out) {
+  return guarded([&] {
+    check_dm(d);
+    if (shots == 0) return;
+    if (!host_out) fail(TANQ_E_ARG, "NULL argument");
+    if (seed >= (1ull << 23)) fail(TANQ_E_ARG, "seed must be below 2^23");
+    if (shots > (1ull << 40)) fail(TANQ_E_ARG, "too many shots");
+    check_readout(d->n, p01, p10);
+    DeviceGuard g(d->device);
+    double* cdf = nullptr;
+    uint64_t* out = nullptr;
+    try {
+      TANQ_HIP(hipMalloc((void**)&cdf, (1ull << d->n) * sizeof(double)));
+      TANQ_HIP(hipMalloc((void**)&out, shots * sizeof(uint64_t)));
+      launch_diag(d->ptr, d->n, d->prec, d->probs_dev, d->partials, d->result_dev, 1, d->stream);
+      if (p01) launch_readout(d->probs_dev, d->n, p01, p10, d->stream);
+      launch_sample(d->probs_dev, d->n, cdf, shots, seed, out, d->stream);
+      TANQ_HIP(hipMemcpyAsync(host_out, out, shots * sizeof(uint64_t), hipMemcpyDeviceToHost, d->stream));
+      TANQ_HIP(hipStreamSynchronize(d->stream));
+    } catch (...) {
+      (void)hipStreamSynchronize(d->stream);
+      dfree(cdf);
+      dfree(out);
+      throw;
+    }
+    dfree(cdf);
+    dfree(out);
+  });
+}
+
+tanq_status tanq_dm_set_basis(tanq_dm d, uint64_t r, uint64_t c) {
+  return guarded([&] {
+    check_dm(d);
+    const uint64_t dim = 1ull << d->n;
+    if (r >= dim || c >= dim) fail(TANQ_E_ARG, "basis index out of range");
+    DeviceGuard g(d->device);
+    launch_init_basis(d->ptr, d->n, d->prec, r + (c << d->n), d->stream);
+  });
+}
+
+tanq_status tanq_reduced_dm(tanq_dm d, int k, const int* keep, double* host_out) {
+  return guarded([&] {
+    check_dm(d);
+    if (!host_out) fail(TANQ_E_ARG, "output is NULL");
+    check_qubits(d->n, k, keep, 4);
+    DeviceGuard g(d->device);
+    int* kd = reinterpret_cast<int*>(d->masks_dev);  // small device scratch of the handle
+    TANQ_HIP(hipMemcpyAsync(kd, keep, k * sizeof(int), hipMemcpyHostToDevice, d->stream));
+    launch_reduced(d->ptr, d->n, d->prec, k, kd, d->result_dev, d->stream);
+    TANQ_HIP(hipMemcpyAsync(host_out, d->result_dev, 2 * ((size_t)1 << (2 * k)) * sizeof(double),
+                            hipMemcpyDeviceToHost, d->stream));
+    TANQ_HIP(hipStreamSynchronize(d->stream));
+  });
+}
+
+// chi_ij = Tr(B_ij^dag S) / 4 with B_ij = conj(sigma_j) (x) sigma_i, the orthogonal basis in which
+// a one-qubit superoperator S = sum_ij chi_ij conj(sigma_j) (x) sigma_i (column stacking; sigma =
+// I, X, Y, Z).  S is 4 x 4 complex, row-major, interleaved.
+static void chi_from_superop(const double* S, double* chi) {
+  static const double sig[4][2][2][2] = {
+      {{{1, 0}, {0, 0}}, {{0, 0}, {1, 0}}},
+      {{{0, 0}, {1, 0}}, {{1, 0}, {0, 0}}},
+      {{{0, 0}, {0, -1}}, {{0, 1}, {0, 0}}},
+      {{{1, 0}, {0, 0}}, {{0, 0}, {-1, 0}}},
+  };
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) {
+      double ar = 0.0, ai = 0.0;
+      // B[(c1 r1)][(c2 r2)] = conj(sig_j[c1][c2]) * sig_i[r1][r2], row index r1 + 2 c1
+      for (int c1 = 0; c1 < 2; ++c1)
+        for (int r1 = 0; r1 < 2; ++r1)
+          for (int c2 = 0; c2 < 2; ++c2)
+            for (int r2 = 0; r2 < 2; ++r2) {
+              const double xr = sig[j][c1][c2][0], xi = -sig[j][c1][c2][1];
+              const double yr = sig[i][r1][r2][0], yi = sig[i][r1][r2][1];
+              const double br = xr * yr - xi * yi, bi = xr * yi + xi * yr;
+              const int row = r1 + 2 * c1, col = r2 + 2 * c2;
+              const double sr = S[2 * (row * 4 + col)], si = S[2 * (row * 4 + col) + 1];
+              // conj(B) * S
+              ar += br * sr + bi * si;
+              ai += br * si - bi * sr;
+            }
+      chi[2 * (i * 4 + j)] = ar / 4.0;
+      chi[2 * (i * 4 + j) + 1] = ai / 4.0;
+    }
+}
+
+tanq_status tanq_process_chi_1q(tanq_circuit c, int max_width, tanq_prec p, int in_qubit, int out_qubit,
+                                double* chi_out, double* superop_out) {
+  return guarded([&] {
+    if (!c || !chi_out) fail(TANQ_E_ARG, "NULL argument");
+    if (in_qubit < 0 || in_qubit >= c->n || out_qubit < 0 || out_qubit >= c->n)
+      fail(TANQ_E_ARG, "qubit out of range");
+    tanq_fused f = nullptr;
+    tanq_dm d = nullptr;
+    auto cleanup = [&] {
+      if (d) tanq_dm_free(d);
+      if (f) tanq_fused_free(f);
+    };
+    try {
+      if (tanq_fuse(c, max_width, p, nullptr, &f) != TANQ_OK) fail(TANQ_E_STATE, tanq_last_error());
+      if (tanq_dm_init(c->n, p, nullptr, &d) != TANQ_OK) fail(TANQ_E_STATE, tanq_last_error());
+      double S[32];
+      for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) {
+          // input |a><b| on in_qubit, |0><0| elsewhere; output reduced to out_qubit
+          if (tanq_dm_set_basis(d, (uint64_t)a << in_qubit, (uint64_t)b << in_qubit) != TANQ_OK ||
+              tanq_apply_fused(d, f) != TANQ_OK)
+            fail(TANQ_E_STATE, tanq_last_error());
+          double red[8];
+          if (tanq_reduced_dm(d, 1, &out_qubit, red) != TANQ_OK) fail(TANQ_E_STATE, tanq_last_error());
+          // column a + 2b of S is vec(E(|a><b|)) = (red[0][0], red[1][0], red[0][1], red[1][1])
+          const int col = a + 2 * b;
+          for (int rr = 0; rr < 2; ++rr)
+            for (int cc = 0; cc < 2; ++cc) {
+              const int row = rr + 2 * cc;
+              S[2 * (row * 4 + col)] = red[2 * (rr * 2 + cc)];
+              S[2 * (row * 4 + col) + 1] = red[2 * (rr * 2 + cc) + 1];
+            }
+        }
+      chi_from_superop(S, chi_out);
+      if (superop_out) std::memcpy(superop_out, S, sizeof(S));
+    } catch (...) {
+      cleanup();
+      throw;
+    }
+    cleanup();
+  });
+}
+
 tanq_status tanq_expect_pauli_batch(tanq_dm d, int count, const char* const* paulis, double* out_re,
                                     double* out_im) {
   return guarded([&] {

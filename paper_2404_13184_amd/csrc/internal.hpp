@@ -140,6 +140,18 @@ void launch_diag(const void* rho, int n, tanq_prec p, double* probs_dev, double*
 void launch_pauli(const void* rho, int n, tanq_prec p, int count, const uint64_t* masks_dev,
                   double* partials, double* result_dev, hipStream_t s);
 
+// vec(rho) = e_idx (rho = |r><c| for idx = r + c 2^n)
+void launch_init_basis(void* rho, int n, tanq_prec p, uint64_t idx, hipStream_t s);
+// Reduced density matrix on k <= 4 kept qubits (device list keep_dev); out_dev: 2 * 4^k doubles
+void launch_reduced(const void* rho, int n, tanq_prec p, int k, const int* keep_dev, double* out_dev, hipStream_t s);
+
+// Classical readout error on the probability vector, one qubit at a time (host arrays p01,
+// p10 of n values), in place.
+void launch_readout(double* probs_dev, int n, const double* p01, const double* p10, hipStream_t s);
+// Inverse-CDF sampling of `shots` outcomes with SplitMix64 draws; cdf_dev: 2^n doubles.
+void launch_sample(const double* probs_dev, int n, double* cdf_dev, uint64_t shots, uint64_t seed, uint64_t* out_dev,
+                   hipStream_t s);
+
 // out3 = (||a-b||_F, max|a-b|, ||a||_F); partials: reduce_partials() doubles.
 void launch_compare(const void* a, tanq_prec pa, const void* b, tanq_prec pb, uint64_t nel, double* partials,
                     double* result_dev, hipStream_t s);

@@ -23,6 +23,13 @@ __global__ void init_zero_kernel(T* __restrict__ rho, uint64_t nreal) {
     rho[i] = (i == 0) ? T(1) : T(0);
 }
 
+// vec(rho) = e_idx: every element zero except element idx = 1 (rho = |r><c|, idx = r + c 2^n)
+template <typename T>
+__global__ void init_basis_kernel(T* __restrict__ rho, uint64_t nreal, uint64_t idx) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nreal; i += (uint64_t)gridDim.x * blockDim.x)
+    rho[i] = (i == 2 * idx) ? T(1) : T(0);
+}
+
 __device__ inline uint64_t splitmix64(uint64_t c) {
   uint64_t z = c + 0x9E3779B97F4A7C15ull;
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
@@ -265,6 +272,104 @@ __global__ void compare_finish_kernel(const double* __restrict__ partials, int n
   }
 }
 
+// Reduced density matrix on the kept qubits: out[a][b] = sum over the other qubits' values f
+// of rho[dep(a) | f][dep(b) | f].  One workgroup per output element (a, b); FP64.
+template <typename T>
+__global__ __launch_bounds__(RED_THREADS) void reduced_kernel(const T* __restrict__ rho, int n, int k,
+                                                             const int* __restrict__ keep,
+                                                             double* __restrict__ out) {
+  __shared__ double sh[RED_THREADS / 64];
+  __shared__ int kq[8];
+  if (threadIdx.x < (unsigned)k) kq[threadIdx.x] = keep[threadIdx.x];
+  __syncthreads();
+  const int D = 1 << k;
+  const int a = blockIdx.x % D, b = blockIdx.x / D;
+  uint64_t ra = 0, rb = 0, kmask = 0;
+  for (int t = 0; t < k; ++t) {
+    kmask |= 1ull << kq[t];
+    if ((a >> t) & 1) ra |= 1ull << kq[t];
+    if ((b >> t) & 1) rb |= 1ull << kq[t];
+  }
+  const uint64_t nf = 1ull << (n - k);
+  double sr = 0.0, si = 0.0;
+  for (uint64_t f = threadIdx.x; f < nf; f += RED_THREADS) {
+    // deposit f into the bits outside kmask
+    uint64_t x = 0, ff = f;
+    for (int bit = 0; bit < n; ++bit)
+      if (!((kmask >> bit) & 1ull)) {
+        x |= (ff & 1ull) << bit;
+        ff >>= 1;
+      }
+    const uint64_t e = (ra | x) + ((rb | x) << n);
+    sr += (double)rho[2 * e];
+    si += (double)rho[2 * e + 1];
+  }
+  const double tr = block_sum(sr, sh);
+  const double ti = block_sum(si, sh);
+  if (threadIdx.x == 0) {
+    out[2 * (a * D + b)] = tr;
+    out[2 * (a * D + b) + 1] = ti;
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// readout error and sampling (FP64, on the probability vector)
+// ------------------------------------------------------------------------------------
+
+// Qubit t is read as 1 when it is 0 with probability p10 and as 0 when it is 1 with p01:
+// q[x with bit t = 0] = (1 - p10) p[.0.] + p01 p[.1.],  q[.1.] = p10 p[.0.] + (1 - p01) p[.1.]
+__global__ void readout_kernel(double* __restrict__ p, uint64_t dim, int t, double p01, double p10) {
+  const uint64_t half = dim >> 1, bit = 1ull << t, low = bit - 1ull;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < half; i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t x0 = ((i & ~low) << 1) | (i & low), x1 = x0 | bit;
+    const double a = p[x0], b = p[x1];
+    p[x0] = (1.0 - p10) * a + p01 * b;
+    p[x1] = p10 * a + (1.0 - p01) * b;
+  }
+}
+
+// Inclusive prefix sums of p[0..dim) by one workgroup of 1024 threads (fixed order).
+__global__ __launch_bounds__(1024) void cdf_kernel(const double* __restrict__ p, uint64_t dim, double* __restrict__ cdf) {
+  __shared__ double part[1024];
+  const uint64_t per = (dim + 1023) / 1024;
+  const uint64_t b = threadIdx.x * per, e = (b + per < dim) ? b + per : dim;
+  double s = 0.0;
+  for (uint64_t x = b; x < e; ++x) s += p[x];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double run = 0.0;
+    for (int i = 0; i < 1024; ++i) {
+      const double v = part[i];
+      part[i] = run;
+      run += v;
+    }
+  }
+  __syncthreads();
+  double run = part[threadIdx.x];
+  for (uint64_t x = b; x < e; ++x) {
+    run += p[x];
+    cdf[x] = run;
+  }
+}
+
+// Shot i draws u = top 53 bits of SplitMix64((seed << 40) + i) in [0, 1) and returns the
+// smallest x with cdf[x] > u * cdf[dim - 1].
+__global__ void sample_kernel(const double* __restrict__ cdf, uint64_t dim, uint64_t shots, uint64_t seed,
+                              uint64_t* __restrict__ out) {
+  const double total = cdf[dim - 1];
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < shots; i += (uint64_t)gridDim.x * blockDim.x) {
+    const double u = (double)(splitmix64((seed << 40) + i) >> 11) * 0x1.0p-53 * total;
+    uint64_t lo = 0, hi = dim - 1;
+    while (lo < hi) {
+      const uint64_t mid = (lo + hi) >> 1;
+      if (cdf[mid] > u) hi = mid;
+      else lo = mid + 1;
+    }
+    out[i] = lo;
+  }
+}
+
 // ------------------------------------------------------------------------------------
 // host-side launchers
 // ------------------------------------------------------------------------------------
@@ -319,6 +424,52 @@ void launch_compose(const FuseBlockDev* blocks, int nblocks, int max_k, const Fu
     hipLaunchKernelGGL(compose_kernel<2>, dim3(nblocks), dim3(256), 0, s, blocks, ops, sops, out);
   else
     hipLaunchKernelGGL(compose_kernel<3>, dim3(nblocks), dim3(256), 0, s, blocks, ops, sops, out);
+  TANQ_HIP(hipGetLastError());
+}
+
+void launch_init_basis(void* rho, int n, tanq_prec p, uint64_t idx, hipStream_t s) {
+  const uint64_t nreal = 2ull << (2 * n);
+  uint64_t blocks = (nreal + 255) / 256;
+  const uint64_t cap = (uint64_t)device_cu_count() * 64;
+  if (blocks > cap) blocks = cap;
+  if (p == TANQ_F64)
+    hipLaunchKernelGGL(init_basis_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, s, (double*)rho, nreal, idx);
+  else
+    hipLaunchKernelGGL(init_basis_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, s, (float*)rho, nreal, idx);
+  TANQ_HIP(hipGetLastError());
+}
+
+void launch_reduced(const void* rho, int n, tanq_prec p, int k, const int* keep_dev, double* out_dev, hipStream_t s) {
+  const unsigned nb = 1u << (2 * k);
+  if (p == TANQ_F64)
+    hipLaunchKernelGGL(reduced_kernel<double>, dim3(nb), dim3(RED_THREADS), 0, s, (const double*)rho, n, k, keep_dev,
+                       out_dev);
+  else
+    hipLaunchKernelGGL(reduced_kernel<float>, dim3(nb), dim3(RED_THREADS), 0, s, (const float*)rho, n, k, keep_dev,
+                       out_dev);
+  TANQ_HIP(hipGetLastError());
+}
+
+void launch_readout(double* probs_dev, int n, const double* p01, const double* p10, hipStream_t s) {
+  const uint64_t dim = 1ull << n;
+  uint64_t blocks = (dim / 2 + 255) / 256;
+  if (blocks > 1024) blocks = 1024;
+  if (blocks < 1) blocks = 1;
+  for (int t = 0; t < n; ++t) {
+    hipLaunchKernelGGL(readout_kernel, dim3((unsigned)blocks), dim3(256), 0, s, probs_dev, dim, t, p01[t], p10[t]);
+    TANQ_HIP(hipGetLastError());
+  }
+}
+
+void launch_sample(const double* probs_dev, int n, double* cdf_dev, uint64_t shots, uint64_t seed, uint64_t* out_dev,
+                   hipStream_t s) {
+  const uint64_t dim = 1ull << n;
+  hipLaunchKernelGGL(cdf_kernel, dim3(1), dim3(1024), 0, s, probs_dev, dim, cdf_dev);
+  TANQ_HIP(hipGetLastError());
+  uint64_t blocks = (shots + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(sample_kernel, dim3((unsigned)blocks), dim3(256), 0, s, cdf_dev, dim, shots, seed, out_dev);
   TANQ_HIP(hipGetLastError());
 }
 

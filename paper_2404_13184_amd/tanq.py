@@ -41,7 +41,9 @@ EXPORTED = [
     "tanq_fuse", "tanq_fuse_plan", "tanq_fused_info", "tanq_fused_free", "tanq_fused_get",
     "tanq_apply_superop", "tanq_apply_fused", "tanq_apply_fused_range",
     "tanq_variant_count", "tanq_variant_get", "tanq_variant_select", "tanq_variant_selected", "tanq_autotune",
-    "tanq_probs", "tanq_expect_pauli", "tanq_expect_pauli_c", "tanq_expect_pauli_batch",
+    "tanq_probs", "tanq_probs_readout", "tanq_sample", "tanq_dm_set_basis", "tanq_reduced_dm",
+    "tanq_process_chi_1q",
+    "tanq_expect_pauli", "tanq_expect_pauli_c", "tanq_expect_pauli_batch",
     "tanq_dm_compare",
     "tanq_server_create", "tanq_server_submit", "tanq_server_poll", "tanq_server_wait", "tanq_server_release",
     "tanq_server_stats_get", "tanq_server_destroy",
@@ -126,6 +128,11 @@ _SIGS = {
     "tanq_variant_selected": ([ctypes.c_int, ctypes.c_int, _ip], ctypes.c_int),
     "tanq_autotune": ([_vp, ctypes.c_int, _dp], ctypes.c_int),
     "tanq_probs": ([_vp, _dp, ctypes.c_int, _dp], ctypes.c_int),
+    "tanq_probs_readout": ([_vp, _dp, _dp, _dp], ctypes.c_int),
+    "tanq_dm_set_basis": ([_vp, ctypes.c_uint64, ctypes.c_uint64], ctypes.c_int),
+    "tanq_reduced_dm": ([_vp, ctypes.c_int, _ip, _dp], ctypes.c_int),
+    "tanq_process_chi_1q": ([_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _dp], ctypes.c_int),
+    "tanq_sample": ([_vp, ctypes.c_uint64, ctypes.c_uint64, _dp, _dp, ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
     "tanq_expect_pauli": ([_vp, ctypes.c_char_p, _dp], ctypes.c_int),
     "tanq_expect_pauli_c": ([_vp, ctypes.c_char_p, _dp, _dp], ctypes.c_int),
     "tanq_expect_pauli_batch": ([_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_char_p), _dp, _dp], ctypes.c_int),
@@ -365,6 +372,47 @@ def tanq_probs(h: int, dim: int, renormalize: bool = True):
     return out, tr.value
 
 
+def tanq_probs_readout(h: int, n: int, p01, p10) -> np.ndarray:
+    a = np.ascontiguousarray(p01, dtype=np.float64)
+    b = np.ascontiguousarray(p10, dtype=np.float64)
+    out = np.empty(1 << n, dtype=np.float64)
+    _check(load().tanq_probs_readout(h, a.ctypes.data_as(_dp), b.ctypes.data_as(_dp), out.ctypes.data_as(_dp)))
+    return out
+
+
+def tanq_dm_set_basis(h: int, r: int, c: int):
+    _check(load().tanq_dm_set_basis(h, r, c))
+
+
+def tanq_reduced_dm(h: int, keep: Sequence[int]) -> np.ndarray:
+    k = len(keep)
+    out = np.empty((1 << k, 1 << k), dtype=np.complex128)
+    _check(load().tanq_reduced_dm(h, k, _ints(keep), out.ctypes.data_as(_dp)))
+    return out
+
+
+def tanq_process_chi_1q(circuit: int, max_width: int, prec, in_qubit: int, out_qubit: int):
+    """(chi, S): the process matrix in the Pauli basis and the 4x4 superoperator."""
+    prec = _prec(prec)
+    chi = np.empty((4, 4), dtype=np.complex128)
+    S = np.empty((4, 4), dtype=np.complex128)
+    _check(load().tanq_process_chi_1q(circuit, max_width, prec, in_qubit, out_qubit, chi.ctypes.data_as(_dp),
+                                      S.ctypes.data_as(_dp)))
+    return chi, S
+
+
+def tanq_sample(h: int, shots: int, seed: int, p01=None, p10=None) -> np.ndarray:
+    out = np.empty(shots, dtype=np.uint64)
+    a = b = None
+    if p01 is not None:
+        a = np.ascontiguousarray(p01, dtype=np.float64)
+        b = np.ascontiguousarray(p10, dtype=np.float64)
+    _check(load().tanq_sample(h, shots, seed, a.ctypes.data_as(_dp) if a is not None else None,
+                              b.ctypes.data_as(_dp) if b is not None else None,
+                              out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))))
+    return out
+
+
 def tanq_expect_pauli(h: int, pauli: str) -> float:
     v = ctypes.c_double()
     _check(load().tanq_expect_pauli(h, pauli.encode(), ctypes.byref(v)))
@@ -529,6 +577,18 @@ class DM:
     def autotune(self, reps: int = 3) -> list:
         return tanq_autotune(self.h, reps)
 
+    def probs_readout(self, p01, p10) -> np.ndarray:
+        return tanq_probs_readout(self.h, self.n, p01, p10)
+
+    def set_basis(self, r: int, c: int):
+        tanq_dm_set_basis(self.h, r, c)
+
+    def reduced(self, keep: Sequence[int]) -> np.ndarray:
+        return tanq_reduced_dm(self.h, keep)
+
+    def sample(self, shots: int, seed: int, p01=None, p10=None) -> np.ndarray:
+        return tanq_sample(self.h, shots, seed, p01, p10)
+
     def expect_pauli(self, pauli: str) -> complex:
         return tanq_expect_pauli_c(self.h, pauli)
 
@@ -544,6 +604,10 @@ class Circuit:
             self.add_arrays(arrays)
         for op in ops:
             self.add(op)
+
+    def process_chi_1q(self, in_qubit: int, out_qubit: int, max_width: int = TANQ_FUSE_AUTO, prec="f64"):
+        """(chi, S) of the one-qubit channel in_qubit -> out_qubit defined by this circuit."""
+        return tanq_process_chi_1q(self.h, max_width, prec, in_qubit, out_qubit)
 
     def add_arrays(self, ca):
         """Append a pooled circuit (workloads.CircuitArrays) in one call."""

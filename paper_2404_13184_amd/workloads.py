@@ -214,9 +214,258 @@ def thermal_relaxation(t1: float, t2: float, t: float) -> List[np.ndarray]:
     return out
 
 
+def generalized_amplitude_damping(gamma: float, excited: float) -> List[np.ndarray]:
+    """Relaxation with rate gamma toward the thermal state diag(1 - excited, excited)."""
+    a, b = math.sqrt(1.0 - excited), math.sqrt(excited)
+    g, h = math.sqrt(gamma), math.sqrt(1.0 - gamma)
+    return [np.array([[a, 0], [0, a * h]], dtype=np.complex128),
+            np.array([[0, a * g], [0, 0]], dtype=np.complex128),
+            np.array([[b * h, 0], [0, b]], dtype=np.complex128),
+            np.array([[0, 0], [b * g, 0]], dtype=np.complex128)]
+
+
+def thermal_relaxation_general(t1: float, t2: float, t: float, excited: float = 0.0) -> List[np.ndarray]:
+    """Thermal relaxation with equilibrium excited-state population ``excited``: populations
+    relax toward diag(1 - excited, excited) as exp(-t/T1), coherences decay as exp(-t/T2)
+    (T2 <= 2 T1).  Generalised amplitude damping followed by phase damping; the Kraus set is the
+    non-zero products.  excited = 0 gives :func:`thermal_relaxation`."""
+    if t2 > 2 * t1:
+        raise ValueError("thermal relaxation needs T2 <= 2 T1")
+    gamma = 1.0 - math.exp(-t / t1)
+    lam = 1.0 - math.exp(-2.0 * t / t2 + t / t1)
+    out = []
+    for P in phase_damping(lam):
+        for A in generalized_amplitude_damping(gamma, excited):
+            K = P @ A
+            if np.abs(K).max() > 0:
+                out.append(K)
+    return out
+
+
+def kraus_compose(first: Sequence[np.ndarray], second: Sequence[np.ndarray]) -> List[np.ndarray]:
+    """Kraus set of the channel `second` after `first` (all products, zero products dropped)."""
+    out = []
+    for B in second:
+        for A in first:
+            K = B @ A
+            if np.abs(K).max() > 0:
+                out.append(K)
+    return out
+
+
+def kraus_tensor(a: Sequence[np.ndarray], b: Sequence[np.ndarray]) -> List[np.ndarray]:
+    """Kraus set of channel a on local qubit 0 and b on local qubit 1 (a is the LSB factor)."""
+    return [np.kron(B, A) for B in b for A in a]
+
+
+def kraus_canonical(kraus: Sequence[np.ndarray], tol: float = 1e-15) -> List[np.ndarray]:
+    """An equivalent Kraus set of at most d^2 operators: eigenvectors of the Choi matrix
+    J = sum_i vec(K_i) vec(K_i)^dag (column stacking), K'_j = sqrt(l_j) unvec(v_j) for the
+    eigenvalues l_j above tol * max(l)."""
+    d = kraus[0].shape[0]
+    vecs = np.stack([np.asarray(K, dtype=np.complex128).T.reshape(-1) for K in kraus], axis=1)
+    J = vecs @ vecs.conj().T
+    J = 0.5 * (J + J.conj().T)
+    w, v = np.linalg.eigh(J)
+    keep = w > tol * max(w.max(), 1e-300)
+    return [math.sqrt(float(w[i])) * v[:, i].reshape(d, d).T for i in np.nonzero(keep)[0][::-1]]
+
+
+def process_fidelity_to_identity(kraus: Sequence[np.ndarray]) -> float:
+    """F_pro = sum_i |Tr K_i|^2 / d^2 (overlap of the channel with the identity channel)."""
+    d = kraus[0].shape[0]
+    return float(sum(abs(np.trace(K)) ** 2 for K in kraus).real) / (d * d)
+
+
+def depolarizing_for_gate_error(gate_error: float, relax: Sequence[np.ndarray]) -> float:
+    """Depolarizing parameter p such that depolarizing(p) after the relaxation channel has
+    average gate infidelity `gate_error` (the device-noise rule of Qiskit-Aer, which the paper
+    follows: the reported gate error is split into relaxation during the gate plus
+    depolarizing).  With F_avg = (d F_pro + 1) / (d + 1) and
+    F_pro(dep_p o R) = (1 - p) F_pro(R) + p / d^2.  Clamped to [0, 4^j / (4^j - 1)]."""
+    d = relax[0].shape[0]
+    f_target = 1.0 - gate_error
+    fpro_target = ((d + 1) * f_target - 1.0) / d
+    fr = process_fidelity_to_identity(relax)
+    if fr - 1.0 / (d * d) <= 0:
+        return 0.0
+    p = (fr - fpro_target) / (fr - 1.0 / (d * d))
+    return min(max(p, 0.0), d * d / (d * d - 1.0))
+
+
 def dephase() -> List[np.ndarray]:
     """Mid-circuit Z-basis measurement with the outcome discarded: complete dephasing."""
     return [np.diag([1.0, 0.0]).astype(np.complex128), np.diag([0.0, 1.0]).astype(np.complex128)]
+
+
+# --------------------------------------------------------------------------------------
+# Device calibration and noise injection into basis circuits (Sec. 3.5, Sec. 4)
+# --------------------------------------------------------------------------------------
+
+
+@dataclasses.dataclass
+class Device:
+    """Calibration of a synthetic device: per-qubit T1, T2 (us), excited-state population,
+    readout errors P(0|1) = p01 and P(1|0) = p10, 1q gate time (us) and error; per-coupler CX
+    time and error.  Couplers are directed (control, target) pairs."""
+
+    n: int
+    t1: np.ndarray
+    t2: np.ndarray
+    excited: np.ndarray
+    p01: np.ndarray
+    p10: np.ndarray
+    t_1q: float
+    err_1q: np.ndarray
+    couplers: List[Tuple[int, int]]
+    t_cx: dict
+    err_cx: dict
+
+
+def synthetic_device(n: int, seed: int = 7, line: bool = True) -> Device:
+    """Seeded calibration in the ranges of current superconducting devices: T1 ~ U[50, 150],
+    T2 ~ U[0.5, 1.5] T1 capped at 2 T1, SX/X time 0.035 us with error ~ U[1e-4, 5e-4], CX
+    time ~ U[0.25, 0.5] us with error ~ U[5e-3, 1.5e-2], readout p01 ~ U[1e-2, 4e-2] (relaxation
+    during readout makes it the larger) and p10 ~ U[5e-3, 2e-2]; couplers on a line (both
+    directions) or all-to-all."""
+    rng = np.random.default_rng(seed)
+    t1 = rng.uniform(50.0, 150.0, n)
+    t2 = np.minimum(rng.uniform(0.5, 1.5, n) * t1, 2.0 * t1)
+    excited = rng.uniform(0.0, 0.02, n)
+    p01 = rng.uniform(1e-2, 4e-2, n)
+    p10 = rng.uniform(5e-3, 2e-2, n)
+    err_1q = rng.uniform(1e-4, 5e-4, n)
+    if line:
+        couplers = [(a, a + 1) for a in range(n - 1)] + [(a + 1, a) for a in range(n - 1)]
+    else:
+        couplers = [(a, b) for a in range(n) for b in range(n) if a != b]
+    t_cx = {c: float(rng.uniform(0.25, 0.5)) for c in couplers}
+    err_cx = {c: float(rng.uniform(5e-3, 1.5e-2)) for c in couplers}
+    return Device(n, t1, t2, excited, p01, p10, 0.035, err_1q, couplers, t_cx, err_cx)
+
+
+def sx() -> np.ndarray:
+    """sqrt(X) = [[1 + i, 1 - i], [1 - i, 1 + i]] / 2."""
+    return np.array([[1 + 1j, 1 - 1j], [1 - 1j, 1 + 1j]], dtype=np.complex128) / 2.0
+
+
+def device_gate_noise(dev: Device, gate: str, qubits: Sequence[int]) -> List[np.ndarray]:
+    """Noise channel that follows a basis gate on the device (Qiskit-Aer's device model):
+    thermal relaxation of every touched qubit for the gate time, then depolarizing with the
+    parameter that makes the total average gate infidelity the reported gate error.  RZ is
+    virtual (no noise, empty list)."""
+    if gate == "rz":
+        return []
+    if gate in ("sx", "x", "id"):
+        q = qubits[0]
+        relax = thermal_relaxation_general(dev.t1[q], dev.t2[q], dev.t_1q, dev.excited[q])
+        p = depolarizing_for_gate_error(float(dev.err_1q[q]), relax)
+        return kraus_canonical(kraus_compose(relax, depolarizing(p, 1)) if p > 0 else relax)
+    if gate == "cx":
+        c, t = qubits
+        tg = dev.t_cx[(c, t)]
+        rc = thermal_relaxation_general(dev.t1[c], dev.t2[c], tg, dev.excited[c])
+        rt = thermal_relaxation_general(dev.t1[t], dev.t2[t], tg, dev.excited[t])
+        relax = kraus_tensor(rc, rt)
+        p = depolarizing_for_gate_error(dev.err_cx[(c, t)], relax)
+        return kraus_canonical(kraus_compose(relax, depolarizing(p, 2)) if p > 0 else relax)
+    raise ValueError(gate)
+
+
+def noisy_basis_circuit(dev: Device, gates: Sequence[Tuple[str, Tuple[int, ...], float]]) -> List[Op]:
+    """Inject the device's noise after every basis gate.  gates: (name, qubits, angle) with
+    name in {"rz", "sx", "x", "id", "cx"} (the angle is used by rz only); CX must be on a
+    coupler of the device."""
+    ops: List[Op] = []
+    for name, qs, ang in gates:
+        if name == "rz":
+            ops.append(gate(rz(ang), qs, "rz"))
+        elif name == "sx":
+            ops.append(gate(sx(), qs, "sx"))
+        elif name == "x":
+            ops.append(gate(PX, qs, "x"))
+        elif name == "id":
+            ops.append(gate(I2, qs, "id"))
+        elif name == "cx":
+            if tuple(qs) not in dev.t_cx:
+                raise ValueError("CX %r is not a coupler of the device" % (tuple(qs),))
+            ops.append(gate(cx(), qs, "cx"))
+        else:
+            raise ValueError(name)
+        noise = device_gate_noise(dev, name, qs)
+        if noise:
+            ops.append(channel(noise, qs, "noise_" + name))
+    return ops
+
+
+def u3_to_basis(q: int, theta: float, phi: float, lam: float) -> List[Tuple[str, Tuple[int, ...], float]]:
+    """U3(theta, phi, lambda) = RZ(phi + pi) SX RZ(theta + pi) SX RZ(lambda) up to global phase."""
+    return [("rz", (q,), lam), ("sx", (q,), 0.0), ("rz", (q,), theta + math.pi), ("sx", (q,), 0.0),
+            ("rz", (q,), phi + math.pi)]
+
+
+def measure_with_readout_error(p01: float, p10: float) -> List[np.ndarray]:
+    """Z-basis measurement whose outcome is kept in the qubit (deferred-measurement form) and
+    misread with P(0|1) = p01, P(1|0) = p10: coherences vanish and the populations pass
+    through the confusion matrix [[1 - p10, p01], [p10, 1 - p01]].  Four Kraus operators
+    sqrt(P(y|x)) |y><x|."""
+    if not (0.0 <= p01 <= 1.0 and 0.0 <= p10 <= 1.0):
+        raise ValueError("readout error out of range")
+    out = []
+    for x in range(2):
+        for y in range(2):
+            w = (p10 if y else 1.0 - p10) if x == 0 else (1.0 - p01 if y else p01)
+            if w > 0.0:
+                K = np.zeros((2, 2), dtype=np.complex128)
+                K[y, x] = math.sqrt(w)
+                out.append(K)
+    return out
+
+
+def with_gate_errors(dev: Device, err_1q: float, err_cx: float) -> Device:
+    """The same device with every 1q gate error set to err_1q and every CX error to err_cx
+    (the 'turned-up' noise of the teleportation case study, Sec. 5)."""
+    return dataclasses.replace(dev, err_1q=np.full(dev.n, float(err_1q)),
+                               err_cx={k: float(err_cx) for k in dev.err_cx})
+
+
+def teleport_device_circuit(dev: Device, a: int, b: int, c: int, u3_in: Tuple[float, float, float] = None,
+                            readout: bool = True) -> List[Op]:
+    """Teleportation of qubit a onto c through the Bell pair (b, c), transpiled to the device's
+    basis {RZ, SX, CX} with the device noise after every basis gate (Sec. 5, case study 1):
+    [U3(a)] H(b) CX(b,c) CX(a,b) H(a), measurement of a and b (kept in the qubits, misread
+    with the device's readout errors when `readout`), then the corrections CX(b,c) and
+    CZ(a,c) = H(c) CX(a,c) H(c).  H = RZ(pi/2) SX RZ(pi/2) up to a global phase.  Needs the
+    couplers (b,c), (a,b) and (a,c)."""
+    def h(q):
+        return [("rz", (q,), math.pi / 2), ("sx", (q,), 0.0), ("rz", (q,), math.pi / 2)]
+
+    ops: List[Op] = []
+    pre = [] if u3_in is None else u3_to_basis(a, *u3_in)
+    ops += noisy_basis_circuit(dev, pre + h(b) + [("cx", (b, c), 0.0), ("cx", (a, b), 0.0)] + h(a))
+    for q in (a, b):
+        p01, p10 = (float(dev.p01[q]), float(dev.p10[q])) if readout else (0.0, 0.0)
+        ops.append(channel(measure_with_readout_error(p01, p10), (q,), "meas"))
+    ops += noisy_basis_circuit(dev, [("cx", (b, c), 0.0)] + h(c) + [("cx", (a, c), 0.0)] + h(c))
+    return ops
+
+
+def device_random_circuit(dev: Device, layers: int, seed: int) -> List[Op]:
+    """Random U3 layers (decomposed into RZ/SX) and CX on random disjoint couplers, with the
+    device's noise after every basis gate."""
+    rng = np.random.default_rng(seed)
+    gates = []
+    for _ in range(layers):
+        for q in range(dev.n):
+            th, ph, la = rng.uniform(0.0, 2 * math.pi, size=3)
+            gates += u3_to_basis(q, th, ph, la)
+        used = set()
+        for idx in rng.permutation(len(dev.couplers)):
+            c, t = dev.couplers[int(idx)]
+            if c not in used and t not in used:
+                gates.append(("cx", (c, t), 0.0))
+                used.update((c, t))
+    return noisy_basis_circuit(dev, gates)
 
 
 # --------------------------------------------------------------------------------------
