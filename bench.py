@@ -27,6 +27,46 @@ FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "apply_kernel_traffic_16q.txt")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2404_13184_amd", "csrc", f) for f in ("apply.hip", "tile.hpp")]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def kernel_name(prec, k, variant) -> str:
+    t = "double" if prec == "f64" else "float"
+    return "apply_tiles_kernel<%s, %d, %d, %d, true>" % (t, k, variant["tile_bits"], variant["threads"])
+
+
+def measured_traffic(name: str):
+    """HBM bytes per launch of `name` from the committed rocprofv3 counter summary (FETCH_SIZE
+    and WRITE_SIZE, each scaled by what the counter reads for a copy kernel of known size), or
+    None when there is no summary for it or the kernel sources changed since it was taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    src_hash, rows = None, {}
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            f = line.split()
+            if len(f) >= 2 and f[0] == "source_hash":
+                src_hash = f[1]
+            elif len(f) >= 4 and f[0] == "kernel":
+                # kernel <name without spaces> <fetch bytes> <write bytes>
+                rows[f[1]] = (float(f[2]), float(f[3]))
+    if src_hash != kernel_source_hash():
+        return None
+    hit = rows.get(name.replace(" ", ""))
+    return None if hit is None else hit[0] + hit[1]
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -45,6 +85,9 @@ def parse():
     ap.add_argument("--serve-steps", type=int, default=8)
     ap.add_argument("--serve-budget-gb", type=float, default=32.0)
     ap.add_argument("--plain-budget-s", type=float, default=30.0)
+    ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
+                    help="first run one device copy of this size (reads and writes it once): the "
+                         "known-size kernel that scales HBM byte counters")
     return ap.parse_args()
 
 
@@ -61,7 +104,7 @@ def run_precision(T, torch, n, ops, prec, width, steps, warmup):
     t0 = time.perf_counter()
     tuned_ms = d.autotune(reps=2)
     d.reset()
-    variants = {k: T.tanq_variant_get(k, T._prec(prec), T.tanq_variant_selected(k, T._prec(prec)))
+    variants = {k: T.tanq_variant_get(k, T._prec(prec), T.tanq_variant_for(n, k, prec))
                 for k in (2, 3) if k <= n}
     log("%s autotune %.1fs: ms/apply by k %s" % (prec, time.perf_counter() - t0, tuned_ms[1:]))
 
@@ -116,9 +159,12 @@ def roofline(prec, k, n, secs):
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel_k": k,
                 "avg_launch_ms": round(secs * 1e3, 3), "algorithmic_bytes": nbytes}
     ach = flops / secs / 1e12
+    # the k = 3 kernel multiplies in 3M form: three real products instead of four
+    executed = 6.0 * (4 ** k) * (4 ** n) if k == 3 else flops
     return {"bound": "mfma", "achieved": round(ach, 2), "peak": peak_f, "unit": "TFLOP/s",
             "frac": round(ach / peak_f, 4), "traffic": None, "kernel_k": k,
             "avg_launch_ms": round(secs * 1e3, 3), "algorithmic_flops": flops,
+            "mfma_flops_executed": executed, "mfma_frac_executed": round(executed / secs / 1e12 / peak_f, 4),
             "hbm_GBs": round(nbytes / secs / 1e9, 1)}
 
 
@@ -252,6 +298,15 @@ def main():
 
     T.load()
     torch.cuda.init()
+    if a.copy_calibration_gib > 0:
+        nel = int(a.copy_calibration_gib * (1 << 30)) // 8
+        src = torch.ones(nel, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: %d bytes read and %d bytes written by one copy kernel" % (nel * 8, nel * 8))
+        del src, dst
     n, ops = W.config4(layers=a.layers, n=a.n)
     results, dms = {}, {}
     for prec in a.precs.split(","):
@@ -274,7 +329,14 @@ def main():
     def dominant(rr, prec):
         k = max(rr["per_k"], key=lambda kk: sum(rr["per_k"][kk]))
         secs = sum(rr["per_k"][k]) / len(rr["per_k"][k])
-        return roofline(prec, k, n, secs)
+        rl = roofline(prec, k, n, secs)
+        if k in rr["variants"]:
+            name = kernel_name(prec, k, rr["variants"][k])
+            rl["kernel"] = name
+            rl["traffic"] = measured_traffic(name)
+            if rl["traffic"] is not None:
+                rl["traffic_unit"] = "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
+        return rl
 
     out = {
         "metric": "16-qubit DM superop applies/s",

@@ -208,11 +208,27 @@ tanq_status tanq_variant_selected(int k, tanq_prec p, int* index);
 
 /* Time every variant of every width k <= min(3, n) on d (reps applies of the identity
  * superoperator on a low and a high qubit placement, so finite contents of d are left
- * unchanged), select the fastest of each width, and record the best milliseconds per apply
- * for (n, precision).  TANQ_FUSE_AUTO then chooses the fusion width that minimises the sum of
- * these costs over the planned blocks.  ms_per_apply (may be NULL) receives 4 values, index
- * k = 1..3 (0 where k > n).  Synchronises. */
+ * unchanged), record the fastest of each width as the variant for (n, k, precision) -- it
+ * takes precedence over the process-wide choice for states of n qubits until the next
+ * tanq_variant_select of that (k, precision) -- and record the best milliseconds per apply.
+ * TANQ_FUSE_AUTO then chooses the fusion width that minimises the sum of these costs over the
+ * planned blocks.  ms_per_apply (may be NULL) receives 4 values, index k = 1..3 (0 where
+ * k > n).  Synchronises. */
 tanq_status tanq_autotune(tanq_dm d, int reps, double* ms_per_apply);
+
+/* The variant applies of width k on n-qubit states use (the autotuned one, else the
+ * process-wide choice). */
+tanq_status tanq_variant_for(int n, int k, tanq_prec p, int* index);
+
+/* The autotuning cache as text, to keep tuning results across processes: one line per tuned
+ * (n, k, precision), "tune <n> <k> <f64|f32> <tile_bits> <threads> <ms per apply>" (tile bits
+ * and threads are 0 for k = 1).  buf may be NULL to query; *len receives the size needed,
+ * including the terminating NUL; E_ARG if cap is smaller. */
+tanq_status tanq_tuning_export(char* buf, size_t cap, size_t* len);
+/* Load text written by tanq_tuning_export (blank lines and lines starting with '#' are
+ * skipped).  Every line is validated first -- E_ARG names a malformed line or a variant this
+ * build does not have -- and nothing changes unless all lines are valid. */
+tanq_status tanq_tuning_import(const char* text);
 
 /* ---------------------------------------------------------------------------------------
  * Measurement statistics (Sec. 2.1: rho gives the probability of every outcome).

@@ -1,6 +1,8 @@
 // C ABI of libtanq (declared in include/tanq.h): handles, circuits, fusion and
 // measurement entry points.  Every compute step runs in the HIP kernels of kernels.hip;
 // this file validates arguments, owns memory and orders work on the handle's stream.
+#include <cstdio>
+#include <mutex>
 #include <algorithm>
 #include <cstring>
 #include <memory>
@@ -387,15 +389,27 @@ tanq_status tanq_circuit_size(tanq_circuit c, int* count) {
 
 namespace {
 
-// Measured milliseconds per apply, per (n, precision, k), filled by tanq_autotune.
+// Measured milliseconds per apply, per (n, precision, k), filled by tanq_autotune or
+// tanq_tuning_import; guarded by g_cost_mu.
 double g_cost_ms[MAX_N + 1][2][4] = {};
+std::mutex g_cost_mu;
+
+double cost_get(int n, tanq_prec p, int k) {
+  std::lock_guard<std::mutex> lk(g_cost_mu);
+  return g_cost_ms[n][p == TANQ_F64 ? 0 : 1][k];
+}
+
+void cost_set(int n, tanq_prec p, int k, double ms) {
+  std::lock_guard<std::mutex> lk(g_cost_mu);
+  g_cost_ms[n][p == TANQ_F64 ? 0 : 1][k] = ms;
+}
 
 // Cost of one apply of width k, used to choose the fusion width when asked to: the
 // autotuned time if there is one for (n, precision), else a model in units of one HBM
 // pass over vec(rho) -- k <= 2 is bound by that pass, k = 3 by MFMA throughput (16 flop/B
 // in FP64 and 32 flop/B in FP32 against machine balances of about 10 and 20 flop/B).
 double apply_cost(int n, int k, tanq_prec p) {
-  const double ms = g_cost_ms[n][p == TANQ_F64 ? 0 : 1][k];
+  const double ms = cost_get(n, p, k);
   if (ms > 0.0) return ms;
   if (k <= 2) return 1.0;
   return 1.65;
@@ -630,6 +644,86 @@ tanq_status tanq_variant_selected(int k, tanq_prec p, int* index) {
   });
 }
 
+tanq_status tanq_variant_for(int n, int k, tanq_prec p, int* index) {
+  return guarded([&] {
+    if (!index) fail(TANQ_E_ARG, "index is NULL");
+    check_prec(p);
+    if (n < 1 || n > MAX_N) fail(TANQ_E_ARG, "n must be in 1..17");
+    if (k == 1) {
+      *index = 0;
+      return;
+    }
+    if (k != 2 && k != 3) fail(TANQ_E_ARG, "k must be 1, 2 or 3");
+    *index = variant_for(n, k, p);
+  });
+}
+
+tanq_status tanq_tuning_export(char* buf, size_t cap, size_t* len) {
+  return guarded([&] {
+    if (!len) fail(TANQ_E_ARG, "len is NULL");
+    std::string out;
+    char line[160];
+    for (int n = 1; n <= MAX_N; ++n)
+      for (int pi = 0; pi < 2; ++pi) {
+        const tanq_prec p = pi == 0 ? TANQ_F64 : TANQ_F32;
+        for (int k = 1; k <= 3; ++k) {
+          const double ms = cost_get(n, p, k);
+          if (!(ms > 0.0)) continue;
+          int tb = 0, th = 0;
+          if (k > 1) variant_describe(k, p, variant_for(n, k, p), &tb, &th);
+          std::snprintf(line, sizeof(line), "tune %d %d %s %d %d %.6g\n", n, k, pi == 0 ? "f64" : "f32", tb, th, ms);
+          out += line;
+        }
+      }
+    *len = out.size() + 1;
+    if (buf) {
+      if (cap < out.size() + 1) fail(TANQ_E_ARG, "buffer too small");
+      std::memcpy(buf, out.c_str(), out.size() + 1);
+    }
+  });
+}
+
+tanq_status tanq_tuning_import(const char* text) {
+  return guarded([&] {
+    if (!text) fail(TANQ_E_ARG, "text is NULL");
+    struct Row {
+      int n, k, variant;
+      tanq_prec p;
+      double ms;
+    };
+    std::vector<Row> rows;
+    const char* cur = text;
+    int lineno = 0;
+    while (*cur) {
+      const char* end = std::strchr(cur, '\n');
+      std::string line = end ? std::string(cur, end) : std::string(cur);
+      cur = end ? end + 1 : cur + line.size();
+      ++lineno;
+      if (line.empty() || line[0] == '#') continue;
+      char prec[8] = {0};
+      int n = 0, k = 0, tb = 0, th = 0;
+      double ms = 0.0;
+      if (std::sscanf(line.c_str(), "tune %d %d %7s %d %d %lf", &n, &k, prec, &tb, &th, &ms) != 6)
+        fail(TANQ_E_ARG, "tuning line " + std::to_string(lineno) + " is malformed");
+      const std::string ps(prec);
+      if (ps != "f64" && ps != "f32") fail(TANQ_E_ARG, "tuning line " + std::to_string(lineno) + ": bad precision");
+      const tanq_prec p = ps == "f64" ? TANQ_F64 : TANQ_F32;
+      if (n < 1 || n > MAX_N || k < 1 || k > 3 || k > n || !(ms > 0.0))
+        fail(TANQ_E_ARG, "tuning line " + std::to_string(lineno) + ": out of range");
+      int v = 0;
+      if (k > 1) {
+        v = variant_find(k, p, tb, th);
+        if (v < 0) fail(TANQ_E_ARG, "tuning line " + std::to_string(lineno) + ": no such variant in this build");
+      }
+      rows.push_back({n, k, v, p, ms});
+    }
+    for (const Row& r : rows) {  // all lines valid: apply them
+      if (r.k > 1) variant_tune(r.n, r.k, r.p, r.variant);
+      cost_set(r.n, r.p, r.k, r.ms);
+    }
+  });
+}
+
 tanq_status tanq_autotune(tanq_dm d, int reps, double* ms_per_apply) {
   return guarded([&] {
     check_dm(d);
@@ -658,16 +752,20 @@ tanq_status tanq_autotune(tanq_dm d, int reps, double* ms_per_apply) {
           hi[t] = n - k + t;
         }
         const int nvar = (k == 1) ? 1 : variant_count(k, p);
-        const int keep = (k == 1) ? 0 : variant_selected(k, p);
-        int best = keep;
+        int best = (k == 1) ? 0 : variant_for(n, k, p);
         double best_t = 1e300;
+        auto run = [&](int v, const int* q) {
+          if (k == 1)
+            launch_apply(d->ptr, n, p, k, q, packed, d->stream);
+          else
+            launch_apply_variant(d->ptr, n, p, k, v, q, packed, d->stream);
+        };
         for (int v = 0; v < nvar; ++v) {
-          if (k > 1) variant_select(k, p, v);
-          launch_apply(d->ptr, n, p, k, lo, packed, d->stream);  // warm-up
+          run(v, lo);  // warm-up
           TANQ_HIP(hipEventRecord(e0, d->stream));
           for (int r = 0; r < reps; ++r) {
-            launch_apply(d->ptr, n, p, k, lo, packed, d->stream);
-            launch_apply(d->ptr, n, p, k, hi, packed, d->stream);
+            run(v, lo);
+            run(v, hi);
           }
           TANQ_HIP(hipEventRecord(e1, d->stream));
           TANQ_HIP(hipEventSynchronize(e1));
@@ -679,9 +777,9 @@ tanq_status tanq_autotune(tanq_dm d, int reps, double* ms_per_apply) {
             best = v;
           }
         }
-        if (k > 1) variant_select(k, p, best);
+        if (k > 1) variant_tune(n, k, p, best);
         best_ms[k] = best_t;
-        g_cost_ms[n][p == TANQ_F64 ? 0 : 1][k] = best_t;
+        cost_set(n, p, k, best_t);
       }
     } catch (...) {
       (void)hipEventDestroy(e0);

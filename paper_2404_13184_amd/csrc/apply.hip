@@ -26,6 +26,7 @@
 // one 16-row m-tile of (Sr, Si, Sr + Si) and a share of the tile's column blocks; a barrier
 // separates the reads of the tile from the in-place LDS writes.
 // k = 1 (the paper's C1, kept off the matrix units as in the paper): VALU over the s_i map.
+#include <atomic>
 #include <cstring>
 #include <type_traits>
 
@@ -40,8 +41,8 @@ namespace tanq {
 template <typename T, int K, int VMAX, int NT, bool FULL>
 __global__ __launch_bounds__(NT) void apply_tiles_kernel(T* __restrict__ rho, const T* __restrict__ frag,
                                                          const ApplyGeom g) {
-  using IO = TileIo<T, VMAX, NT, FULL>;
-  using Op = std::conditional_t<K == 2, Op2<T, NT>, Op3<T, VMAX, NT>>;
+  using IO = TileIo<T, VMAX, NT>;
+  using Op = std::conditional_t<K == 2, Op2<T, VMAX, NT>, Op3<T, VMAX, NT>>;
   using c2 = typename Mfma<T>::c2;
 
   __shared__ u32x4 lds[IO::SLOTS];
@@ -56,6 +57,7 @@ __global__ __launch_bounds__(NT) void apply_tiles_kernel(T* __restrict__ rho, co
     op.load(frag, lane);
   else
     op.load(frag, lane, wave);
+  op.prepare(g, lane, wave);
 
   uint64_t tile = blockIdx.x;
   if (tile >= g.ntiles) return;  // uniform per workgroup
@@ -63,11 +65,11 @@ __global__ __launch_bounds__(NT) void apply_tiles_kernel(T* __restrict__ rho, co
   u32x4 buf[IO::ITERS];
 #pragma unroll
   for (int it = 0; it < IO::ITERS; ++it)
-    if (io.has(it, tid)) buf[it] = *reinterpret_cast<const u32x4*>(rho + 2 * (cur + io.off[it]));
+    if (io.template has<FULL>(it, tid)) buf[it] = *reinterpret_cast<const u32x4*>(rho + 2 * (cur + io.off[it]));
 #pragma unroll
   for (int it = 0; it < IO::ITERS; ++it)
-    if (io.has(it, tid)) lds[io.lslot[it]] = buf[it];
-  __syncthreads();
+    if (io.template has<FULL>(it, tid)) lds[io.lslot[it]] = buf[it];
+  lds_barrier();
 
   for (;;) {
     const uint64_t next = tile + gridDim.x;
@@ -77,24 +79,24 @@ __global__ __launch_bounds__(NT) void apply_tiles_kernel(T* __restrict__ rho, co
       nbase = tile_base(g, next);
 #pragma unroll
       for (int it = 0; it < IO::ITERS; ++it)
-        if (io.has(it, tid)) buf[it] = *reinterpret_cast<const u32x4*>(rho + 2 * (nbase + io.off[it]));
+        if (io.template has<FULL>(it, tid)) buf[it] = *reinterpret_cast<const u32x4*>(rho + 2 * (nbase + io.off[it]));
     }
 
     if constexpr (K == 2)
-      op.compute(reinterpret_cast<T*>(lds), g, lane, wave);
+      op.template compute<FULL>(reinterpret_cast<T*>(lds), g, lane, wave);
     else
-      op.compute(reinterpret_cast<c2*>(lds), g, lane, wave);
-    __syncthreads();
+      op.template compute<FULL>(reinterpret_cast<c2*>(lds), g, lane, wave);
+    lds_barrier();
 
 #pragma unroll
     for (int it = 0; it < IO::ITERS; ++it)
-      if (io.has(it, tid)) *reinterpret_cast<u32x4*>(rho + 2 * (cur + io.off[it])) = lds[io.lslot[it]];
+      if (io.template has<FULL>(it, tid)) *reinterpret_cast<u32x4*>(rho + 2 * (cur + io.off[it])) = lds[io.lslot[it]];
     if (!more) break;
-    __syncthreads();  // every store-phase LDS read is done before the next tile lands
+    lds_barrier();  // every store-phase LDS read is done before the next tile lands
 #pragma unroll
     for (int it = 0; it < IO::ITERS; ++it)
-      if (io.has(it, tid)) lds[io.lslot[it]] = buf[it];
-    __syncthreads();
+      if (io.template has<FULL>(it, tid)) lds[io.lslot[it]] = buf[it];
+    lds_barrier();
     tile = next;
     cur = nbase;
   }
@@ -355,14 +357,30 @@ static const VariantEntry kVariants[] = {
     {3, TANQ_F64, 12, 512, launch_variant<double, 3, 12, 512>},
     {3, TANQ_F64, 11, 256, launch_variant<double, 3, 11, 256>},
     {3, TANQ_F64, 11, 512, launch_variant<double, 3, 11, 512>},
+    {3, TANQ_F64, 10, 256, launch_variant<double, 3, 10, 256>},
     {3, TANQ_F32, 12, 512, launch_variant<float, 3, 12, 512>},
     {3, TANQ_F32, 12, 256, launch_variant<float, 3, 12, 256>},
     {3, TANQ_F32, 13, 512, launch_variant<float, 3, 13, 512>},
+    {3, TANQ_F32, 11, 256, launch_variant<float, 3, 11, 256>},
 };
 constexpr int kNumVariants = (int)(sizeof(kVariants) / sizeof(kVariants[0]));
 
-// selected variant per (k, precision), as an index among that pair's variants
-static int g_selected[4][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+// Process-wide variant per (k, precision), as an index among that pair's variants, and the
+// autotuned variant per (n, k, precision) (-1: none), which takes precedence for that n.
+static std::atomic<int> g_selected[4][2];
+static std::atomic<int> g_tuned[kTunedMaxN + 1][2][4];
+
+static struct VariantTablesInit {
+  VariantTablesInit() {
+    for (auto& a : g_selected)
+      for (auto& b : a) b.store(0);
+    for (auto& a : g_tuned)
+      for (auto& b : a)
+        for (auto& c : b) c.store(-1);
+  }
+} g_variant_tables_init;
+
+static inline int pidx(tanq_prec p) { return p == TANQ_F64 ? 0 : 1; }
 
 static int variant_global_index(int k, tanq_prec p, int local) {
   int c = 0;
@@ -389,13 +407,46 @@ bool variant_describe(int k, tanq_prec p, int local, int* tile_bits, int* thread
   return true;
 }
 
+int variant_find(int k, tanq_prec p, int tile_bits, int threads) {
+  int c = 0;
+  for (int i = 0; i < kNumVariants; ++i)
+    if (kVariants[i].k == k && kVariants[i].p == p) {
+      if (kVariants[i].tile_bits == tile_bits && kVariants[i].threads == threads) return c;
+      ++c;
+    }
+  return -1;
+}
+
 bool variant_select(int k, tanq_prec p, int local) {
   if (variant_global_index(k, p, local) < 0) return false;
-  g_selected[k][p == TANQ_F64 ? 0 : 1] = local;
+  g_selected[k][pidx(p)].store(local);
+  for (int n = 0; n <= kTunedMaxN; ++n) g_tuned[n][pidx(p)][k].store(-1);  // an explicit choice wins
   return true;
 }
 
-int variant_selected(int k, tanq_prec p) { return g_selected[k][p == TANQ_F64 ? 0 : 1]; }
+int variant_selected(int k, tanq_prec p) { return g_selected[k][pidx(p)].load(); }
+
+bool variant_tune(int n, int k, tanq_prec p, int local) {
+  if (n < 1 || n > kTunedMaxN || (local >= 0 && variant_global_index(k, p, local) < 0)) return false;
+  g_tuned[n][pidx(p)][k].store(local);
+  return true;
+}
+
+int variant_tuned(int n, int k, tanq_prec p) {
+  return (n >= 1 && n <= kTunedMaxN) ? g_tuned[n][pidx(p)][k].load() : -1;
+}
+
+int variant_for(int n, int k, tanq_prec p) {
+  const int t = variant_tuned(n, k, p);
+  return t >= 0 ? t : variant_selected(k, p);
+}
+
+void launch_apply_variant(void* rho, int n, tanq_prec p, int k, int local, const int* qubits, const void* packed,
+                          hipStream_t s) {
+  const int gi = variant_global_index(k, p, local);
+  if (gi < 0) fail(TANQ_E_ARG, "no such apply variant");
+  kVariants[gi].fn(rho, n, qubits, packed, s);
+}
 
 void launch_apply(void* rho, int n, tanq_prec p, int k, const int* qubits, const void* packed, hipStream_t s) {
   if (k == 1) {
@@ -413,8 +464,7 @@ void launch_apply(void* rho, int n, tanq_prec p, int k, const int* qubits, const
     return;
   }
   if (k != 2 && k != 3) fail(TANQ_E_ARG, "superoperator width must be 1, 2 or 3");
-  const int gi = variant_global_index(k, p, variant_selected(k, p));
-  kVariants[gi].fn(rho, n, qubits, packed, s);
+  launch_apply_variant(rho, n, p, k, variant_for(n, k, p), qubits, packed, s);
 }
 
 void launch_pack(const FuseBlockDev* blocks, int nblocks, const double* raw, void* packed, tanq_prec p,

@@ -11,13 +11,56 @@
 
 namespace tanq {
 
+// The tiles [t0, t1) of one item, in place: the next tile is prefetched into registers while
+// the current one is multiplied in LDS, as in the single-state kernel.
+template <bool FULL, typename T, typename IO, typename Op, typename G>
+__device__ inline void batch_tiles(T* __restrict__ rho, const IO& io, const Op& op, const G& g, u32x4* lds,
+                                   uint32_t t0, uint32_t t1, int tid, int lane, int wave) {
+  using c2 = typename Mfma<T>::c2;
+  uint64_t cur = tile_base(g, t0);
+  u32x4 buf[IO::ITERS];
+#pragma unroll
+  for (int it = 0; it < IO::ITERS; ++it)
+    if (io.template has<FULL>(it, tid)) buf[it] = *reinterpret_cast<const u32x4*>(rho + 2 * (cur + io.off[it]));
+#pragma unroll
+  for (int it = 0; it < IO::ITERS; ++it)
+    if (io.template has<FULL>(it, tid)) lds[io.lslot[it]] = buf[it];
+  lds_barrier();
+  for (uint32_t t = t0;;) {
+    const bool more = t + 1 < t1;
+    uint64_t nbase = 0;
+    if (more) {
+      nbase = tile_base(g, t + 1);
+#pragma unroll
+      for (int it = 0; it < IO::ITERS; ++it)
+        if (io.template has<FULL>(it, tid))
+          buf[it] = *reinterpret_cast<const u32x4*>(rho + 2 * (nbase + io.off[it]));
+    }
+    if constexpr (std::is_same_v<Op, Op2<T, Op::kVmax, Op::kThreads>>)
+      op.template compute<FULL>(reinterpret_cast<T*>(lds), g, lane, wave);
+    else
+      op.template compute<FULL>(reinterpret_cast<c2*>(lds), g, lane, wave);
+    lds_barrier();
+#pragma unroll
+    for (int it = 0; it < IO::ITERS; ++it)
+      if (io.template has<FULL>(it, tid)) *reinterpret_cast<u32x4*>(rho + 2 * (cur + io.off[it])) = lds[io.lslot[it]];
+    lds_barrier();  // every store-phase LDS read is done before the next tile lands (or the next chunk)
+    if (!more) break;
+#pragma unroll
+    for (int it = 0; it < IO::ITERS; ++it)
+      if (io.template has<FULL>(it, tid)) lds[io.lslot[it]] = buf[it];
+    lds_barrier();
+    ++t;
+    cur = nbase;
+  }
+}
+
 template <typename T, int K, int VMAX, int NT>
 __global__ __launch_bounds__(NT) void batch_apply_kernel(const BatchItem* __restrict__ items,
                                                          const BatchChunk* __restrict__ chunks,
                                                          const uint32_t* __restrict__ count) {
-  using IO = TileIo<T, VMAX, NT, false>;
-  using Op = std::conditional_t<K == 2, Op2<T, NT>, Op3<T, VMAX, NT>>;
-  using c2 = typename Mfma<T>::c2;
+  using IO = TileIo<T, VMAX, NT>;
+  using Op = std::conditional_t<K == 2, Op2<T, VMAX, NT>, Op3<T, VMAX, NT>>;
   static_assert(sizeof(ApplyGeom) % 4 == 0, "geometry copied as dwords");
 
   __shared__ u32x4 lds[IO::SLOTS];
@@ -29,17 +72,18 @@ __global__ __launch_bounds__(NT) void batch_apply_kernel(const BatchItem* __rest
   const uint32_t nch = *count;
 
   uint32_t cur = 0xffffffffu;
+  bool full = false;
   IO io;
   Op op;
   T* rho = nullptr;
   for (uint32_t c = blockIdx.x; c < nch; c += gridDim.x) {
     const BatchChunk ch = chunks[c];
     if (ch.item != cur) {
-      __syncthreads();  // the previous item's geometry is no longer read
+      lds_barrier();  // the previous item's geometry is no longer read
       const uint32_t* src = reinterpret_cast<const uint32_t*>(&items[ch.item].g);
       uint32_t* dst = reinterpret_cast<uint32_t*>(&sg);
       for (int i = tid; i < (int)(sizeof(ApplyGeom) / 4); i += NT) dst[i] = src[i];
-      __syncthreads();
+      lds_barrier();
       rho = reinterpret_cast<T*>(items[ch.item].rho);
       const T* frag = reinterpret_cast<const T*>(items[ch.item].frag);
       io.init(sg, tid);
@@ -47,28 +91,15 @@ __global__ __launch_bounds__(NT) void batch_apply_kernel(const BatchItem* __rest
         op.load(frag, lane);
       else
         op.load(frag, lane, wave);
+      op.prepare(sg, lane, wave);
+      full = __builtin_amdgcn_readfirstlane(sg.V) == VMAX;
       cur = ch.item;
     }
-    for (uint32_t t = ch.tile_begin; t < ch.tile_end; ++t) {
-      const uint64_t base = tile_base(sg, t);
-      u32x4 buf[IO::ITERS];
-#pragma unroll
-      for (int it = 0; it < IO::ITERS; ++it)
-        if (io.has(it, tid)) buf[it] = *reinterpret_cast<const u32x4*>(rho + 2 * (base + io.off[it]));
-#pragma unroll
-      for (int it = 0; it < IO::ITERS; ++it)
-        if (io.has(it, tid)) lds[io.lslot[it]] = buf[it];
-      __syncthreads();
-      if constexpr (K == 2)
-        op.compute(reinterpret_cast<T*>(lds), sg, lane, wave);
-      else
-        op.compute(reinterpret_cast<c2*>(lds), sg, lane, wave);
-      __syncthreads();
-#pragma unroll
-      for (int it = 0; it < IO::ITERS; ++it)
-        if (io.has(it, tid)) *reinterpret_cast<u32x4*>(rho + 2 * (base + io.off[it])) = lds[io.lslot[it]];
-      __syncthreads();
-    }
+    if (ch.tile_begin >= ch.tile_end) continue;
+    if (full)
+      batch_tiles<true, T>(rho, io, op, sg, lds, ch.tile_begin, ch.tile_end, tid, lane, wave);
+    else
+      batch_tiles<false, T>(rho, io, op, sg, lds, ch.tile_begin, ch.tile_end, tid, lane, wave);
   }
 }
 

@@ -109,6 +109,14 @@ int variant_count(int k, tanq_prec p);
 bool variant_describe(int k, tanq_prec p, int index, int* tile_bits, int* threads);
 bool variant_select(int k, tanq_prec p, int index);
 int variant_selected(int k, tanq_prec p);
+// autotuned variant per (n, k, precision); -1 = none (the process-wide choice applies)
+constexpr int kTunedMaxN = 17;
+bool variant_tune(int n, int k, tanq_prec p, int index);
+int variant_tuned(int n, int k, tanq_prec p);
+int variant_for(int n, int k, tanq_prec p);
+int variant_find(int k, tanq_prec p, int tile_bits, int threads);
+void launch_apply_variant(void* rho, int n, tanq_prec p, int k, int index, const int* qubits, const void* packed,
+                          hipStream_t s);
 
 void launch_init_zero(void* rho, int n, tanq_prec p, hipStream_t s);
 void launch_gather(const void* rho, tanq_prec p, const uint64_t* idx_dev, size_t count, void* out_dev,

@@ -67,8 +67,9 @@ __device__ inline uint32_t swz(uint32_t e, const G& g) {
 }
 
 // Global element offset and swizzled LDS slot of every 16-byte slot a thread moves; the same
-// for every tile of one geometry.  FULL: the tile has all 2^VMAX elements, so no per-slot guard.
-template <typename T, int VMAX, int NT, bool FULL>
+// for every tile of one geometry.  has<true>: the tile has all 2^VMAX elements, so no
+// per-slot guard (a guard around each access makes the compiler drain every load in turn).
+template <typename T, int VMAX, int NT>
 struct TileIo {
   static constexpr int EPS = 16 / (2 * (int)sizeof(T));  // elements per 16-byte slot
   static constexpr int SLOTS = (1 << VMAX) / EPS;
@@ -79,16 +80,17 @@ struct TileIo {
 
   template <typename G>
   __device__ inline void init(const G& g, int tid) {
-    slots = FULL ? SLOTS : (1 << g.V) / EPS;
+    slots = (1 << g.V) / EPS;
 #pragma unroll
     for (int it = 0; it < ITERS; ++it) {
       const uint32_t j = (uint32_t)((it * NT + tid) * EPS);
       uint64_t o = 0;
-      for (int b = 0; b < (FULL ? VMAX : g.V); ++b) o |= (uint64_t)((j >> b) & 1u) << g.vpos[b];
+      for (int b = 0; b < g.V; ++b) o |= (uint64_t)((j >> b) & 1u) << g.vpos[b];
       off[it] = o;
       lslot[it] = (j ^ swz(j, g)) / EPS;
     }
   }
+  template <bool FULL>
   __device__ inline bool has(int it, int tid) const { return FULL || it * NT + tid < slots; }
 };
 
@@ -101,19 +103,41 @@ __device__ inline uint64_t tile_base(const G& g, uint64_t tile) {
   return b;
 }
 
+// Workgroup barrier for LDS traffic only: LDS writes before it are visible to every wave after
+// it, while global loads and stores stay in flight across it (a full __syncthreads also waits
+// for every outstanding global access, which would serialise the tile pipeline).
+__device__ inline void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // ------------------------------------------------------------------------------------
 // k = 2: real-block form.  Interleaved data is a real vector of length 32 and S the 32 x 32
 // real matrix [[Sr, -Si], [Si, Sr]] (interleaved); each wave owns 16-group column blocks and
 // all of S: 2 m-tiles x 8 k-steps of 16x16x4 MFMA per block.  In place, no barrier inside:
-// a wave reads and writes only its own groups.
+// a wave reads and writes only its own groups.  prepare() computes everything that depends
+// only on the geometry and the lane (group offsets, swizzle, row offsets) once per launch.
+// compute<true>: every tile holds 2^VMAX elements, so every lane of every column block is a
+// group.  LDS reads are never guarded (a guarded read puts a full LDS wait before every MFMA):
+// in partial tiles the lanes past the last group read group 0 and write nothing.
 // ------------------------------------------------------------------------------------
-template <typename T, int NT>
+template <typename T, int VMAX, int NT>
 struct Op2 {
+  static constexpr int kVmax = VMAX, kThreads = NT;
   using M = Mfma<T>;
   using acc_t = typename M::acc_t;
   using c2 = typename M::c2;
   static constexpr int MT = 2, KS = 8;
+  static constexpr int NW = NT / 64;
+  static constexpr int NB_MAX = (1 << (VMAX - 4)) / 16;  // column blocks of a full tile
+  static constexpr int NBW = (NB_MAX + NW - 1) / NW;     // column blocks per wave
+  static_assert(NB_MAX % NW == 0, "full tiles give every wave the same number of blocks");
   T afr[MT][KS];
+  uint32_t gj[NBW], xg[NBW];
+  bool act[NBW];
+  uint32_t tj1, tq;
+  int nblk;
 
   __device__ inline void load(const T* __restrict__ frag, int lane) {
 #pragma unroll
@@ -123,44 +147,52 @@ struct Op2 {
   }
 
   template <typename G>
-  __device__ inline void compute(T* ldsT, const G& g, int lane, int wave) const {
-    constexpr int NW = NT / 64;
+  __device__ inline void prepare(const G& g, int lane, int wave) {
     const int GG = g.G;
-    const int nblk = (GG + 15) >> 4;
+    nblk = (GG + 15) >> 4;
     const int kk = lane >> 4;
-    const int hb = kk >> 1;                  // low bit of the B row's complex index
-    const int cc = kk & 1;                   // re / im of the B row
-    const uint32_t tj1 = hb ? g.tj[1] : 0u;  // tile-local part contributed by that bit
-    const uint32_t tq = g.tj[2 * kk];        // f32: outputs 2 kk and 2 kk + 1 of each m-tile
-    for (int nb = wave; nb < nblk; nb += NW) {
-      const int gi = nb * 16 + (lane & 15);
-      const bool act = gi < GG;
-      const uint32_t gj = act ? pdep32((uint32_t)gi, g.free_mask) : 0u;
-      const uint32_t xg = swz(gj, g);
+    tj1 = (kk >> 1) ? g.tj[1] : 0u;  // tile-local part of the B row's low complex bit
+    tq = g.tj[2 * kk];                // f32: outputs 2 kk and 2 kk + 1 of each m-tile
+#pragma unroll
+    for (int i = 0; i < NBW; ++i) {
+      const int gi = (wave + i * NW) * 16 + (lane & 15);
+      act[i] = gi < GG;
+      gj[i] = act[i] ? pdep32((uint32_t)gi, g.free_mask) : 0u;
+      xg[i] = swz(gj[i], g);
+    }
+  }
+
+  template <bool FULL, typename G>
+  __device__ inline void compute(T* ldsT, const G& g, int lane, int wave) const {
+    const int cc = (lane >> 4) & 1;  // re / im of the B row
+#pragma unroll
+    for (int i = 0; i < NBW; ++i) {
+      if (!FULL && wave + i * NW >= nblk) break;  // uniform per wave
       acc_t acc[MT];
 #pragma unroll
       for (int m = 0; m < MT; ++m) acc[m] = acc_t{0, 0, 0, 0};
+      // inactive lanes (partial tiles only) read group 0, which is in the tile, and write nothing
 #pragma unroll
       for (int s = 0; s < KS; ++s) {
-        const uint32_t e = ((g.tj[2 * s] + tj1) ^ xg) + gj;
-        const T b = act ? ldsT[2 * e + cc] : T(0);
+        const uint32_t e = ((g.tj[2 * s] + tj1) ^ xg[i]) + gj[i];
+        const T b = ldsT[2 * e + cc];
 #pragma unroll
         for (int m = 0; m < MT; ++m) acc[m] = M::mma(afr[m][s], b, acc[m]);
       }
-      if (act) {
+      if (FULL || act[i]) {
 #pragma unroll
         for (int m = 0; m < MT; ++m) {
           if constexpr (M::kRowsStrided) {
             // value r = real row kk + 4r of m-tile m: component cc of output a = 8m + 2r + hb
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-              const uint32_t e = ((g.tj[8 * m] + g.tj[2 * r] + tj1) ^ xg) + gj;
+              const uint32_t e = ((g.tj[8 * m] + g.tj[2 * r] + tj1) ^ xg[i]) + gj[i];
               ldsT[2 * e + cc] = acc[m][r];
             }
           } else {
             // values (0,1), (2,3) = (re, im) of outputs a = 8m + 2kk and a + 1
-            const uint32_t e0 = ((g.tj[8 * m] + tq) ^ xg) + gj;
-            const uint32_t e1 = ((g.tj[8 * m] + tq + g.tj[1]) ^ xg) + gj;
+            const uint32_t e0 = ((g.tj[8 * m] + tq) ^ xg[i]) + gj[i];
+            const uint32_t e1 = ((g.tj[8 * m] + tq + g.tj[1]) ^ xg[i]) + gj[i];
             *reinterpret_cast<c2*>(ldsT + 2 * e0) = c2{acc[m][0], acc[m][1]};
             *reinterpret_cast<c2*>(ldsT + 2 * e1) = c2{acc[m][2], acc[m][3]};
           }
@@ -174,10 +206,11 @@ struct Op2 {
 // k = 3: 3M form, P1 = Sr xr, P2 = Si xi, P3 = (Sr + Si)(xr + xi); Re = P1 - P2,
 // Im = P3 - P1 - P2: three real 64 x 64 products instead of four.  Each wave holds one
 // 16-row m-tile of (Sr, Si, Sr + Si) and a share of the tile's column blocks.  compute()
-// contains one barrier: every wave reads the whole tile before the outputs overwrite it.
+// contains one LDS barrier: every wave reads the whole tile before the outputs overwrite it.
 // ------------------------------------------------------------------------------------
 template <typename T, int VMAX, int NT>
 struct Op3 {
+  static constexpr int kVmax = VMAX, kThreads = NT;
   using M = Mfma<T>;
   using acc_t = typename M::acc_t;
   using c2 = typename M::c2;
@@ -186,8 +219,13 @@ struct Op3 {
   static constexpr int NPART = NW / 4;                         // waves sharing one m-tile
   static constexpr int NB_MAX = (1 << (VMAX - 6)) / 16;        // column blocks per full tile
   static constexpr int NBW = (NB_MAX + NPART - 1) / NPART;     // column blocks per wave
+  static_assert(NB_MAX % NPART == 0, "full tiles give every wave the same number of blocks");
   static constexpr int KS = 16;                                // 64 complex columns, steps of 4
   T ar[KS], ai[KS], as[KS];
+  uint32_t gj[NBW], xg[NBW];
+  bool act[NBW];
+  uint32_t tjk, trow0, tjm;
+  int nblk;
 
   __device__ inline void load(const T* __restrict__ frag, int lane, int wave) {
     const int mt = wave & 3;
@@ -200,32 +238,37 @@ struct Op3 {
   }
 
   template <typename G>
-  __device__ inline void compute(c2* ldsC, const G& g, int lane, int wave) const {
-    const int mt = wave & 3, part = wave >> 2;
+  __device__ inline void prepare(const G& g, int lane, int wave) {
     const int GG = g.G;
-    const int nblk = (GG + 15) >> 4;
-    const int kk = lane >> 4;
-    const uint32_t tjk = g.tj[kk];       // B row 4s + kk: tj[4s] + tj[kk]
-    const uint32_t tj4k = g.tj[4 * kk];  // f32 output rows 4 kk + r
-    const uint32_t tjm = g.tj[16 * mt];  // this wave's output block
-    acc_t p1[NBW], p2[NBW], p3[NBW];
-    uint32_t gjs[NBW], xgs[NBW];
-    bool acts[NBW];
+    nblk = (GG + 15) >> 4;
+    const int kk = lane >> 4, part = wave >> 2;
+    tjk = g.tj[kk];                                      // B row 4s + kk: tj[4s] + tj[kk]
+    trow0 = M::kRowsStrided ? g.tj[kk] : g.tj[4 * kk];   // output row kk + 4r (f64), 4kk + r (f32)
+    tjm = g.tj[16 * (wave & 3)];                         // this wave's output m-tile
 #pragma unroll
     for (int i = 0; i < NBW; ++i) {
-      const int nb = part + i * NPART;
-      const int gi = nb * 16 + (lane & 15);
-      acts[i] = nb < nblk && gi < GG;
-      gjs[i] = acts[i] ? pdep32((uint32_t)gi, g.free_mask) : 0u;
-      xgs[i] = swz(gjs[i], g);
+      const int gi = (part + i * NPART) * 16 + (lane & 15);
+      act[i] = gi < GG;
+      gj[i] = act[i] ? pdep32((uint32_t)gi, g.free_mask) : 0u;
+      xg[i] = swz(gj[i], g);
+    }
+  }
+
+  template <bool FULL, typename G>
+  __device__ inline void compute(c2* ldsC, const G& g, int lane, int wave) const {
+    const int part = wave >> 2;
+    acc_t p1[NBW], p2[NBW], p3[NBW];
+#pragma unroll
+    for (int i = 0; i < NBW; ++i) {
       p1[i] = acc_t{0, 0, 0, 0};
       p2[i] = acc_t{0, 0, 0, 0};
       p3[i] = acc_t{0, 0, 0, 0};
-      if (nb < nblk) {
+      if (FULL || part + i * NPART < nblk) {
+        // inactive lanes (partial tiles only) read group 0, which is in the tile, and write nothing
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
-          const uint32_t e = ((g.tj[4 * s] + tjk) ^ xgs[i]) + gjs[i];
-          const c2 v = acts[i] ? ldsC[e] : c2{0, 0};
+          const uint32_t e = ((g.tj[4 * s] + tjk) ^ xg[i]) + gj[i];
+          const c2 v = ldsC[e];
           const T br = v[0], bi = v[1];
           const T bs = br + bi;
           p1[i] = M::mma(ar[s], br, p1[i]);
@@ -234,15 +277,14 @@ struct Op3 {
         }
       }
     }
-    __syncthreads();  // every wave has read the whole tile before outputs overwrite it
+    lds_barrier();  // every wave has read the whole tile before outputs overwrite it
 #pragma unroll
     for (int i = 0; i < NBW; ++i) {
-      if (acts[i]) {
+      if ((FULL || part + i * NPART < nblk) && act[i]) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          // output row within the m-tile: kk + 4r (f64) or 4kk + r (f32)
-          const uint32_t trow = M::kRowsStrided ? (tjk + g.tj[4 * r]) : (tj4k + g.tj[r]);
-          const uint32_t e = ((tjm + trow) ^ xgs[i]) + gjs[i];
+          const uint32_t trow = trow0 + (M::kRowsStrided ? g.tj[4 * r] : g.tj[r]);
+          const uint32_t e = ((tjm + trow) ^ xg[i]) + gj[i];
           const T re = p1[i][r] - p2[i][r];
           const T im = p3[i][r] - p1[i][r] - p2[i][r];
           ldsC[e] = c2{re, im};

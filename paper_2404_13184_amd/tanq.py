@@ -41,6 +41,7 @@ EXPORTED = [
     "tanq_fuse", "tanq_fuse_plan", "tanq_fused_info", "tanq_fused_free", "tanq_fused_get",
     "tanq_apply_superop", "tanq_apply_fused", "tanq_apply_fused_range",
     "tanq_variant_count", "tanq_variant_get", "tanq_variant_select", "tanq_variant_selected", "tanq_autotune",
+    "tanq_variant_for", "tanq_tuning_export", "tanq_tuning_import",
     "tanq_probs", "tanq_probs_readout", "tanq_sample", "tanq_dm_set_basis", "tanq_reduced_dm",
     "tanq_process_chi_1q",
     "tanq_expect_pauli", "tanq_expect_pauli_c", "tanq_expect_pauli_batch",
@@ -130,6 +131,9 @@ _SIGS = {
     "tanq_probs": ([_vp, _dp, ctypes.c_int, _dp], ctypes.c_int),
     "tanq_probs_readout": ([_vp, _dp, _dp, _dp], ctypes.c_int),
     "tanq_dm_set_basis": ([_vp, ctypes.c_uint64, ctypes.c_uint64], ctypes.c_int),
+    "tanq_variant_for": ([ctypes.c_int, ctypes.c_int, ctypes.c_int, _ip], ctypes.c_int),
+    "tanq_tuning_export": ([ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "tanq_tuning_import": ([ctypes.c_char_p], ctypes.c_int),
     "tanq_reduced_dm": ([_vp, ctypes.c_int, _ip, _dp], ctypes.c_int),
     "tanq_process_chi_1q": ([_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _dp], ctypes.c_int),
     "tanq_sample": ([_vp, ctypes.c_uint64, ctypes.c_uint64, _dp, _dp, ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
@@ -378,6 +382,24 @@ def tanq_probs_readout(h: int, n: int, p01, p10) -> np.ndarray:
     out = np.empty(1 << n, dtype=np.float64)
     _check(load().tanq_probs_readout(h, a.ctypes.data_as(_dp), b.ctypes.data_as(_dp), out.ctypes.data_as(_dp)))
     return out
+
+
+def tanq_variant_for(n: int, k: int, prec) -> int:
+    v = ctypes.c_int()
+    _check(load().tanq_variant_for(n, k, _prec(prec), ctypes.byref(v)))
+    return v.value
+
+
+def tanq_tuning_export() -> str:
+    need = ctypes.c_size_t()
+    _check(load().tanq_tuning_export(None, 0, ctypes.byref(need)))
+    buf = ctypes.create_string_buffer(need.value)
+    _check(load().tanq_tuning_export(buf, need.value, ctypes.byref(need)))
+    return buf.value.decode()
+
+
+def tanq_tuning_import(text: str):
+    _check(load().tanq_tuning_import(text.encode()))
 
 
 def tanq_dm_set_basis(h: int, r: int, c: int):
