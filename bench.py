@@ -84,6 +84,8 @@ def parse():
     ap.add_argument("--serve-slots", type=int, default=64)
     ap.add_argument("--serve-steps", type=int, default=8)
     ap.add_argument("--serve-budget-gb", type=float, default=32.0)
+    ap.add_argument("--serve-cohort-mib", type=float, default=0.0,
+                    help="states advanced together per scheduler iteration (0 = all resident requests)")
     ap.add_argument("--plain-budget-s", type=float, default=30.0)
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
                     help="first run one device copy of this size (reads and writes it once): the "
@@ -223,9 +225,9 @@ def _latency_summary(lat, done, first_arrival, last_done):
             "circuits_per_s": round(done / span, 2)}
 
 
-def serve_batched(T, W, reqs, arrays, prec, width, budget, slots, steps):
+def serve_batched(T, W, reqs, arrays, prec, width, budget, slots, steps, cohort_bytes=0):
     """Open-loop replay of the stream through the continuous-batching server."""
-    srv = T.Server(budget, slots, prec, width, steps, use_graphs=True)
+    srv = T.Server(budget, slots, prec, width, steps, use_graphs=True, cohort_bytes=cohort_bytes)
     outs = {}
     t0 = time.perf_counter()
     c0 = srv.stats()["clock"]
@@ -376,7 +378,7 @@ def main():
         reqs, arrays = serving_requests(W, a.serve_requests)
         log("serving: FP32 continuous batching ...")
         batched = serve_batched(T, W, reqs, arrays, "f32", a.serve_width, int(a.serve_budget_gb * (1 << 30)),
-                                a.serve_slots, a.serve_steps)
+                                a.serve_slots, a.serve_steps, int(a.serve_cohort_mib * (1 << 20)))
         log("serving batched: %s" % batched)
         log("serving: plain FP64 per request ...")
         plain = serve_plain(T, W, reqs, arrays, a.plain_budget_s)
@@ -384,7 +386,8 @@ def main():
         out["serving"] = {"workload": "%d requests, Poisson 200/s, n ~ U{4..12}, depth ~ U{20..200}, "
                                       "U3/CX, Ising Trotter and teleport blocks" % a.serve_requests,
                           "batched_f32": dict(batched, width=a.serve_width, slots=a.serve_slots,
-                                              steps_per_launch=a.serve_steps),
+                                              steps_per_launch=a.serve_steps,
+                                              cohort_mib=a.serve_cohort_mib),
                           "plain_f64": plain}
     if not a.no_cpu_baseline:
         log("cpu baseline (oracle) ...")

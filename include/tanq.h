@@ -315,6 +315,11 @@ typedef struct {
   int width;            /* fusion width 2 or 3 (0 = 2) */
   int steps_per_launch; /* batched applies per scheduler iteration, 1..64 */
   int use_graphs;       /* nonzero: replay the iteration's launches from a captured hipGraph */
+  size_t cohort_bytes;  /* 0: every resident request advances in every iteration.  Otherwise each
+                           iteration advances a cohort of resident requests, taken round-robin,
+                           whose states total at most cohort_bytes (at least one request), so
+                           that the iteration's consecutive passes over those states can hit the
+                           device's last-level cache */
 } tanq_server_config;
 
 typedef struct {

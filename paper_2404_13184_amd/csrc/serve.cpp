@@ -174,6 +174,7 @@ struct tanq_server_s {
   std::condition_variable cv_submit, cv_done;
   std::deque<ServeRequest*> pending;
   std::vector<ServeRequest*> active;
+  size_t rr_next = 0;  // cohort scheduling: where the next cohort starts in `active`
   std::unordered_map<uint64_t, std::unique_ptr<ServeRequest>> all;
   std::vector<int> free_slots;
   uint64_t next_ticket = 1;
@@ -296,11 +297,29 @@ void tanq_server_s::run_iteration() {
   if (work_ev_used[b]) TANQ_HIP(hipEventSynchronize(work_ev[b]));  // buffer b's last copy is done
   unsigned char* W = work_host[b];
   std::vector<ServeRequest*> done_now;
+  // the requests this iteration advances: all of them, or a round-robin cohort whose states
+  // total at most cohort_bytes
+  std::vector<ServeRequest*> cohort;
+  if (cfg.cohort_bytes == 0 || active.size() <= 1) {
+    cohort = active;
+  } else {
+    const tanq_prec p = (tanq_prec)cfg.prec;
+    if (rr_next >= active.size()) rr_next = 0;
+    size_t bytes = 0;
+    for (size_t i = 0; i < active.size(); ++i) {
+      ServeRequest* r = active[(rr_next + i) % active.size()];
+      const size_t sb = state_bytes(r->n, p);
+      if (!cohort.empty() && bytes + sb > cfg.cohort_bytes) break;
+      cohort.push_back(r);
+      bytes += sb;
+    }
+    rr_next = (rr_next + cohort.size()) % active.size();
+  }
   for (int s = 0; s < S; ++s) {
     uint32_t ni = 0, nc = 0;
     BatchItem* items = step_items(W, s);
     BatchChunk* chunks = step_chunks(W, s);
-    for (ServeRequest* r : active) {
+    for (ServeRequest* r : cohort) {
       if (r->cursor >= r->geom.size()) continue;
       const ApplyGeom& g = r->geom[r->cursor];
       BatchItem& it = items[ni];

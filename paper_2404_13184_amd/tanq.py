@@ -63,7 +63,8 @@ class Variant(ctypes.Structure):
 
 class ServerConfig(ctypes.Structure):
     _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_slots", ctypes.c_int), ("prec", ctypes.c_int),
-                ("width", ctypes.c_int), ("steps_per_launch", ctypes.c_int), ("use_graphs", ctypes.c_int)]
+                ("width", ctypes.c_int), ("steps_per_launch", ctypes.c_int), ("use_graphs", ctypes.c_int),
+                ("cohort_bytes", ctypes.c_size_t)]
 
 
 class Outputs(ctypes.Structure):
@@ -464,8 +465,9 @@ def tanq_dm_compare(a: int, b: int):
 
 
 def tanq_server_create(hbm_budget: int, max_slots: int, prec: int, width: int = 2,
-                       steps_per_launch: int = 8, use_graphs: bool = True) -> int:
-    cfg = ServerConfig(hbm_budget, max_slots, prec, width, steps_per_launch, int(bool(use_graphs)))
+                       steps_per_launch: int = 8, use_graphs: bool = True, cohort_bytes: int = 0) -> int:
+    cfg = ServerConfig(hbm_budget, max_slots, prec, width, steps_per_launch, int(bool(use_graphs)),
+                       int(cohort_bytes))
     h = _vp()
     _check(load().tanq_server_create(ctypes.byref(cfg), ctypes.byref(h)))
     return h.value
@@ -703,8 +705,9 @@ class Server:
     """Continuous-batching server (see tanq_server_* in include/tanq.h)."""
 
     def __init__(self, hbm_budget: int, max_slots: int = 64, prec="f32", width: int = 2,
-                 steps_per_launch: int = 8, use_graphs: bool = True):
-        self.h = tanq_server_create(hbm_budget, max_slots, _prec(prec), width, steps_per_launch, use_graphs)
+                 steps_per_launch: int = 8, use_graphs: bool = True, cohort_bytes: int = 0):
+        self.h = tanq_server_create(hbm_budget, max_slots, _prec(prec), width, steps_per_launch, use_graphs,
+                                    cohort_bytes)
 
     def submit(self, n: int, ops: Iterable = (), probs: bool = True, paulis: Sequence[str] = (), arrays=None) -> int:
         c = Circuit(n, ops, arrays=arrays)

@@ -47,15 +47,16 @@ def test_server_results_match_oracle(oracle_mod, prec, width):
         assert st["completed"] == len(reqs) and st["bytes_in_use"] == 0
 
 
-@pytest.mark.parametrize("use_graphs", [True, False])
-def test_alone_equals_in_mix(use_graphs):
+@pytest.mark.parametrize("use_graphs,cohort", [(True, 0), (False, 0), (True, 1 * MiB)])
+def test_alone_equals_in_mix(use_graphs, cohort):
     reqs = small_requests(24, seed=77, n_range=(4, 9), depth_range=(3, 12))
     target = reqs[5]
-    say("alone vs mix, graphs=%s" % use_graphs)
+    say("alone vs mix, graphs=%s cohort=%d" % (use_graphs, cohort))
     with T.Server(512 * MiB, max_slots=16, prec="f32", width=2, steps_per_launch=8, use_graphs=use_graphs) as srv:
         t = srv.submit(target[0], target[1], probs=True, paulis=W.z_paulis(target[0]))
         alone = srv.wait(t)
-    with T.Server(512 * MiB, max_slots=16, prec="f32", width=2, steps_per_launch=8, use_graphs=use_graphs) as srv:
+    with T.Server(512 * MiB, max_slots=16, prec="f32", width=2, steps_per_launch=8, use_graphs=use_graphs,
+                  cohort_bytes=cohort) as srv:
         tickets = [srv.submit(n, ops, probs=True, paulis=W.z_paulis(n)) for n, ops, _ in reqs]
         mixed = [srv.wait(t) for t in tickets]
     got = mixed[5]
