@@ -43,6 +43,8 @@ def kernel_source_hash() -> str:
 
 def kernel_name(prec, k, variant) -> str:
     t = "double" if prec == "f64" else "float"
+    if variant.get("staging", 0) == 1:
+        return "apply_dma_kernel<%s, %d, %d, %d>" % (t, k, variant["tile_bits"], variant["threads"])
     return "apply_tiles_kernel<%s, %d, %d, %d, true>" % (t, k, variant["tile_bits"], variant["threads"])
 
 
