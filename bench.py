@@ -82,7 +82,7 @@ def parse():
     ap.add_argument("--cpu-n", type=int, default=12)
     ap.add_argument("--cpu-budget-s", type=float, default=20.0)
     ap.add_argument("--serve-requests", type=int, default=5000, help="0 skips the serving stream")
-    ap.add_argument("--serve-width", type=int, default=2)
+    ap.add_argument("--serve-width", type=int, default=3)
     ap.add_argument("--serve-slots", type=int, default=64)
     ap.add_argument("--serve-steps", type=int, default=8)
     ap.add_argument("--serve-budget-gb", type=float, default=32.0)

@@ -197,6 +197,8 @@ typedef struct {
   int prec;       /* tanq_prec */
   int tile_bits;  /* log2 of the elements one workgroup stages per tile */
   int threads;    /* workgroup size */
+  int staging;    /* 0: tiles staged through registers; 1: direct global-to-LDS loads into two
+                     LDS buffers (full tiles; partial tiles use staging 0) */
 } tanq_variant_t;
 
 /* Number of apply-kernel variants for width k (2 or 3) and precision p; k = 1 has one. */
@@ -221,8 +223,8 @@ tanq_status tanq_autotune(tanq_dm d, int reps, double* ms_per_apply);
 tanq_status tanq_variant_for(int n, int k, tanq_prec p, int* index);
 
 /* The autotuning cache as text, to keep tuning results across processes: one line per tuned
- * (n, k, precision), "tune <n> <k> <f64|f32> <tile_bits> <threads> <ms per apply>" (tile bits
- * and threads are 0 for k = 1).  buf may be NULL to query; *len receives the size needed,
+ * (n, k, precision), "tune <n> <k> <f64|f32> <tile_bits> <threads> <staging> <ms per apply>"
+ * (tile bits, threads and staging are 0 for k = 1).  buf may be NULL to query; *len receives the size needed,
  * including the terminating NUL; E_ARG if cap is smaller. */
 tanq_status tanq_tuning_export(char* buf, size_t cap, size_t* len);
 /* Load text written by tanq_tuning_export (blank lines and lines starting with '#' are

@@ -611,12 +611,12 @@ tanq_status tanq_variant_get(int k, tanq_prec p, int index, tanq_variant_t* out)
     check_prec(p);
     if (k == 1) {
       if (index != 0) fail(TANQ_E_ARG, "k = 1 has one variant");
-      *out = tanq_variant_t{1, (int)p, 0, 256};
+      *out = tanq_variant_t{1, (int)p, 0, 256, 0};
       return;
     }
-    int tb = 0, th = 0;
-    if ((k != 2 && k != 3) || !variant_describe(k, p, index, &tb, &th)) fail(TANQ_E_ARG, "no such variant");
-    *out = tanq_variant_t{k, (int)p, tb, th};
+    int tb = 0, th = 0, st = 0;
+    if ((k != 2 && k != 3) || !variant_describe(k, p, index, &tb, &th, &st)) fail(TANQ_E_ARG, "no such variant");
+    *out = tanq_variant_t{k, (int)p, tb, th, st};
   });
 }
 
@@ -669,9 +669,10 @@ tanq_status tanq_tuning_export(char* buf, size_t cap, size_t* len) {
         for (int k = 1; k <= 3; ++k) {
           const double ms = cost_get(n, p, k);
           if (!(ms > 0.0)) continue;
-          int tb = 0, th = 0;
-          if (k > 1) variant_describe(k, p, variant_for(n, k, p), &tb, &th);
-          std::snprintf(line, sizeof(line), "tune %d %d %s %d %d %.6g\n", n, k, pi == 0 ? "f64" : "f32", tb, th, ms);
+          int tb = 0, th = 0, st = 0;
+          if (k > 1) variant_describe(k, p, variant_for(n, k, p), &tb, &th, &st);
+          std::snprintf(line, sizeof(line), "tune %d %d %s %d %d %d %.6g\n", n, k, pi == 0 ? "f64" : "f32", tb, th,
+                        st, ms);
           out += line;
         }
       }
@@ -701,9 +702,9 @@ tanq_status tanq_tuning_import(const char* text) {
       ++lineno;
       if (line.empty() || line[0] == '#') continue;
       char prec[8] = {0};
-      int n = 0, k = 0, tb = 0, th = 0;
+      int n = 0, k = 0, tb = 0, th = 0, st = 0;
       double ms = 0.0;
-      if (std::sscanf(line.c_str(), "tune %d %d %7s %d %d %lf", &n, &k, prec, &tb, &th, &ms) != 6)
+      if (std::sscanf(line.c_str(), "tune %d %d %7s %d %d %d %lf", &n, &k, prec, &tb, &th, &st, &ms) != 7)
         fail(TANQ_E_ARG, "tuning line " + std::to_string(lineno) + " is malformed");
       const std::string ps(prec);
       if (ps != "f64" && ps != "f32") fail(TANQ_E_ARG, "tuning line " + std::to_string(lineno) + ": bad precision");
@@ -712,7 +713,7 @@ tanq_status tanq_tuning_import(const char* text) {
         fail(TANQ_E_ARG, "tuning line " + std::to_string(lineno) + ": out of range");
       int v = 0;
       if (k > 1) {
-        v = variant_find(k, p, tb, th);
+        v = variant_find(k, p, tb, th, st);
         if (v < 0) fail(TANQ_E_ARG, "tuning line " + std::to_string(lineno) + ": no such variant in this build");
       }
       rows.push_back({n, k, v, p, ms});

@@ -102,6 +102,89 @@ __global__ __launch_bounds__(NT) void apply_tiles_kernel(T* __restrict__ rho, co
   }
 }
 
+// The same multiplication with the tiles staged by direct global-to-LDS loads into two LDS
+// buffers: the next tile streams into one buffer while the current one is multiplied in the
+// other, without passing through registers (which frees the prefetch registers and keeps the
+// HBM reads in flight for the whole multiplication).  Full tiles only.  The waits count this
+// wave's vector-memory operations in issue order: previous tile's stores, then the next
+// tile's loads, are allowed to remain outstanding.
+template <typename T, int K, int VMAX, int NT>
+__global__ __launch_bounds__(NT) void apply_dma_kernel(T* __restrict__ rho, const T* __restrict__ frag,
+                                                       const ApplyGeom g) {
+  using IO = TileDma<T, VMAX, NT>;
+  using Op = std::conditional_t<K == 2, Op2<T, VMAX, NT>, Op3<T, VMAX, NT>>;
+  using c2 = typename Mfma<T>::c2;
+
+  __shared__ u32x4 lds[2][IO::SLOTS];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  IO io;
+  io.init(g, tid);
+  Op op;
+  if constexpr (K == 2)
+    op.load(frag, lane);
+  else
+    op.load(frag, lane, wave);
+  op.prepare(g, lane, wave);
+
+  uint64_t tile = blockIdx.x;
+  if (tile >= g.ntiles) return;  // uniform per workgroup
+  uint64_t cur = tile_base(g, tile);
+  io.load(rho, cur, lds[0], tid, wave);
+  int b = 0;
+  bool first = true;
+  for (;;) {
+    const uint64_t next = tile + gridDim.x;
+    const bool more = next < g.ntiles;
+    uint64_t nbase = 0;
+    if (more) {
+      nbase = tile_base(g, next);
+      io.load(rho, nbase, lds[b ^ 1], tid, wave);
+      if (first)
+        vm_wait<IO::ITERS>();
+      else
+        vm_wait<2 * IO::ITERS>();
+    } else {
+      if (first)
+        vm_wait<0>();
+      else
+        vm_wait<IO::ITERS>();
+    }
+    raw_barrier();  // this tile is in LDS for every wave
+
+    if constexpr (K == 2)
+      op.template compute<true, true>(reinterpret_cast<T*>(lds[b]), g, lane, wave);
+    else
+      op.template compute<true, true>(reinterpret_cast<c2*>(lds[b]), g, lane, wave);
+    raw_barrier();
+
+    io.store(rho, cur, lds[b], tid);
+    if (!more) break;
+    raw_barrier();  // every wave's reads of buffer b are done before it is refilled
+    tile = next;
+    cur = nbase;
+    b ^= 1;
+    first = false;
+  }
+}
+
+// The direct-staging instances of the variant table, instantiated explicitly (implicit
+// instantiation through the launch table did not emit every host-side kernel handle).
+#define TANQ_DMA_INSTANCE(T, K, V, NT) \
+  template __global__ void apply_dma_kernel<T, K, V, NT>(T*, const T*, const ApplyGeom);
+TANQ_DMA_INSTANCE(double, 2, 11, 256)
+TANQ_DMA_INSTANCE(double, 2, 12, 512)
+TANQ_DMA_INSTANCE(double, 3, 12, 512)
+TANQ_DMA_INSTANCE(double, 3, 11, 512)
+TANQ_DMA_INSTANCE(double, 3, 10, 256)
+TANQ_DMA_INSTANCE(float, 2, 12, 256)
+TANQ_DMA_INSTANCE(float, 2, 13, 512)
+TANQ_DMA_INSTANCE(float, 3, 12, 256)
+TANQ_DMA_INSTANCE(float, 3, 11, 256)
+#undef TANQ_DMA_INSTANCE
+
 // ------------------------------------------------------------------------------------
 // C1 apply (k = 1): VALU, one group of four amplitudes per thread
 // ------------------------------------------------------------------------------------
@@ -276,6 +359,9 @@ ApplyGeom make_apply_geom(int n, int k, const int* q, int vbits, tanq_prec p) {
       xd &= ~(1u << (31 - __builtin_clz(xd)));
       --nd;
     }
+    // source bits lie above the window and destination bits inside it, so the map is an
+    // involution (the direct-to-LDS staging relies on that)
+    if (xs & xd) fail(TANQ_E_STATE, "LDS swizzle masks overlap");
     g.xsrc = xs;
     g.xdst = xd;
   }
@@ -325,12 +411,34 @@ static void launch_tiles(const ApplyGeom& g, void* rho, const void* frag, hipStr
 }
 
 template <typename T, int K, int VMAX, int NT>
+static void launch_dma(const ApplyGeom& g, void* rho, const void* frag, hipStream_t s) {
+  auto kern = apply_dma_kernel<T, K, VMAX, NT>;
+  static thread_local int cap_dev = -1;
+  static thread_local uint64_t cap = 0;
+  int dev = 0;
+  TANQ_HIP(hipGetDevice(&dev));
+  if (cap_dev != dev) {
+    cap = persistent_cap(kern, NT);
+    cap_dev = dev;
+  }
+  const uint64_t grid = g.ntiles < cap ? g.ntiles : cap;
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(NT), 0, s, (T*)rho, (const T*)frag, g);
+  TANQ_HIP(hipGetLastError());
+}
+
+// STAGING 0: register prefetch (apply_tiles_kernel); 1: direct global-to-LDS loads into two
+// LDS buffers (apply_dma_kernel) for full tiles, the register kernel for partial ones.
+template <typename T, int K, int VMAX, int NT, int STAGING>
 static void launch_variant(void* rho, int n, const int* qubits, const void* frag, hipStream_t s) {
   const ApplyGeom g = make_apply_geom(n, K, qubits, VMAX, sizeof(T) == 8 ? TANQ_F64 : TANQ_F32);
-  if (g.V == VMAX)
-    launch_tiles<T, K, VMAX, NT, true>(g, rho, frag, s);
-  else
+  if (g.V == VMAX) {
+    if constexpr (STAGING == 1)
+      launch_dma<T, K, VMAX, NT>(g, rho, frag, s);
+    else
+      launch_tiles<T, K, VMAX, NT, true>(g, rho, frag, s);
+  } else {
     launch_tiles<T, K, VMAX, NT, false>(g, rho, frag, s);
+  }
 }
 
 typedef void (*apply_fn)(void*, int, const int*, const void*, hipStream_t);
@@ -340,28 +448,38 @@ struct VariantEntry {
   tanq_prec p;
   int tile_bits;
   int threads;
+  int staging;
   apply_fn fn;
 };
 
 // Apply-kernel variants (tile bits x workgroup size); the first of each (k, precision) is the
 // default until the autotuner or the caller selects another.
 static const VariantEntry kVariants[] = {
-    {2, TANQ_F64, 10, 256, launch_variant<double, 2, 10, 256>},
-    {2, TANQ_F64, 11, 256, launch_variant<double, 2, 11, 256>},
-    {2, TANQ_F64, 11, 512, launch_variant<double, 2, 11, 512>},
-    {2, TANQ_F64, 12, 512, launch_variant<double, 2, 12, 512>},
-    {2, TANQ_F32, 11, 256, launch_variant<float, 2, 11, 256>},
-    {2, TANQ_F32, 12, 256, launch_variant<float, 2, 12, 256>},
-    {2, TANQ_F32, 12, 512, launch_variant<float, 2, 12, 512>},
-    {2, TANQ_F32, 13, 512, launch_variant<float, 2, 13, 512>},
-    {3, TANQ_F64, 12, 512, launch_variant<double, 3, 12, 512>},
-    {3, TANQ_F64, 11, 256, launch_variant<double, 3, 11, 256>},
-    {3, TANQ_F64, 11, 512, launch_variant<double, 3, 11, 512>},
-    {3, TANQ_F64, 10, 256, launch_variant<double, 3, 10, 256>},
-    {3, TANQ_F32, 12, 512, launch_variant<float, 3, 12, 512>},
-    {3, TANQ_F32, 12, 256, launch_variant<float, 3, 12, 256>},
-    {3, TANQ_F32, 13, 512, launch_variant<float, 3, 13, 512>},
-    {3, TANQ_F32, 11, 256, launch_variant<float, 3, 11, 256>},
+    {2, TANQ_F64, 10, 256, 0, launch_variant<double, 2, 10, 256, 0>},
+    {2, TANQ_F64, 11, 256, 0, launch_variant<double, 2, 11, 256, 0>},
+    {2, TANQ_F64, 11, 512, 0, launch_variant<double, 2, 11, 512, 0>},
+    {2, TANQ_F64, 12, 512, 0, launch_variant<double, 2, 12, 512, 0>},
+    {2, TANQ_F64, 11, 256, 1, launch_variant<double, 2, 11, 256, 1>},
+    {2, TANQ_F64, 12, 512, 1, launch_variant<double, 2, 12, 512, 1>},
+    {2, TANQ_F32, 11, 256, 0, launch_variant<float, 2, 11, 256, 0>},
+    {2, TANQ_F32, 12, 256, 0, launch_variant<float, 2, 12, 256, 0>},
+    {2, TANQ_F32, 12, 512, 0, launch_variant<float, 2, 12, 512, 0>},
+    {2, TANQ_F32, 13, 512, 0, launch_variant<float, 2, 13, 512, 0>},
+    {2, TANQ_F32, 12, 256, 1, launch_variant<float, 2, 12, 256, 1>},
+    {2, TANQ_F32, 13, 512, 1, launch_variant<float, 2, 13, 512, 1>},
+    {3, TANQ_F64, 12, 512, 0, launch_variant<double, 3, 12, 512, 0>},
+    {3, TANQ_F64, 11, 256, 0, launch_variant<double, 3, 11, 256, 0>},
+    {3, TANQ_F64, 11, 512, 0, launch_variant<double, 3, 11, 512, 0>},
+    {3, TANQ_F64, 10, 256, 0, launch_variant<double, 3, 10, 256, 0>},
+    {3, TANQ_F64, 12, 512, 1, launch_variant<double, 3, 12, 512, 1>},
+    {3, TANQ_F64, 11, 512, 1, launch_variant<double, 3, 11, 512, 1>},
+    {3, TANQ_F64, 10, 256, 1, launch_variant<double, 3, 10, 256, 1>},
+    {3, TANQ_F32, 12, 512, 0, launch_variant<float, 3, 12, 512, 0>},
+    {3, TANQ_F32, 12, 256, 0, launch_variant<float, 3, 12, 256, 0>},
+    {3, TANQ_F32, 13, 512, 0, launch_variant<float, 3, 13, 512, 0>},
+    {3, TANQ_F32, 11, 256, 0, launch_variant<float, 3, 11, 256, 0>},
+    {3, TANQ_F32, 12, 256, 1, launch_variant<float, 3, 12, 256, 1>},
+    {3, TANQ_F32, 11, 256, 1, launch_variant<float, 3, 11, 256, 1>},
 };
 constexpr int kNumVariants = (int)(sizeof(kVariants) / sizeof(kVariants[0]));
 
@@ -399,19 +517,21 @@ int variant_count(int k, tanq_prec p) {
   return c;
 }
 
-bool variant_describe(int k, tanq_prec p, int local, int* tile_bits, int* threads) {
+bool variant_describe(int k, tanq_prec p, int local, int* tile_bits, int* threads, int* staging) {
   const int gi = variant_global_index(k, p, local);
   if (gi < 0) return false;
   if (tile_bits) *tile_bits = kVariants[gi].tile_bits;
   if (threads) *threads = kVariants[gi].threads;
+  if (staging) *staging = kVariants[gi].staging;
   return true;
 }
 
-int variant_find(int k, tanq_prec p, int tile_bits, int threads) {
+int variant_find(int k, tanq_prec p, int tile_bits, int threads, int staging) {
   int c = 0;
   for (int i = 0; i < kNumVariants; ++i)
     if (kVariants[i].k == k && kVariants[i].p == p) {
-      if (kVariants[i].tile_bits == tile_bits && kVariants[i].threads == threads) return c;
+      if (kVariants[i].tile_bits == tile_bits && kVariants[i].threads == threads && kVariants[i].staging == staging)
+        return c;
       ++c;
     }
   return -1;

@@ -106,7 +106,7 @@ ApplyGeom make_apply_geom(int n, int k, const int* qubits, int vbits, tanq_prec 
 
 // Apply-kernel variants per (k, precision), k in {2, 3}: count, shape, process-wide choice.
 int variant_count(int k, tanq_prec p);
-bool variant_describe(int k, tanq_prec p, int index, int* tile_bits, int* threads);
+bool variant_describe(int k, tanq_prec p, int index, int* tile_bits, int* threads, int* staging);
 bool variant_select(int k, tanq_prec p, int index);
 int variant_selected(int k, tanq_prec p);
 // autotuned variant per (n, k, precision); -1 = none (the process-wide choice applies)
@@ -114,7 +114,7 @@ constexpr int kTunedMaxN = 17;
 bool variant_tune(int n, int k, tanq_prec p, int index);
 int variant_tuned(int n, int k, tanq_prec p);
 int variant_for(int n, int k, tanq_prec p);
-int variant_find(int k, tanq_prec p, int tile_bits, int threads);
+int variant_find(int k, tanq_prec p, int tile_bits, int threads, int staging);
 void launch_apply_variant(void* rho, int n, tanq_prec p, int k, int index, const int* qubits, const void* packed,
                           hipStream_t s);
 

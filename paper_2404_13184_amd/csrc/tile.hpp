@@ -112,6 +112,67 @@ __device__ inline void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// Workgroup barrier without memory fences, for kernels that fill LDS with direct
+// global-to-LDS loads: a fence would also wait for those in-flight loads.  The empty asm
+// statements keep the compiler from moving memory accesses across it; the explicit lgkmcnt(0)
+// completes this wave's own LDS reads and writes first.
+__device__ inline void raw_barrier() {
+  __asm__ __volatile__("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0); vmcnt and expcnt not waited for
+  __builtin_amdgcn_s_barrier();
+  __asm__ __volatile__("" ::: "memory");
+}
+
+// Wait until at most N vector-memory operations of this wave are outstanding (in issue order).
+template <int N>
+__device__ inline void vm_wait() {
+  static_assert(N >= 0 && N < 64, "vmcnt is six bits");
+  __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
+}
+
+template <bool RAW>
+__device__ inline void tile_barrier() {
+  if constexpr (RAW)
+    raw_barrier();
+  else
+    lds_barrier();
+}
+
+// Direct global-to-LDS staging (gfx950 global_load_lds_dwordx4): each lane's 16-byte load
+// lands in LDS at the wave's base + 16 * lane, so LDS slot it * NT + tid is filled from the
+// tile element that the swizzle maps there.  The swizzle is an involution (it only flips
+// bits inside the bank window, chosen by bits above it), so the element held by LDS element j
+// is j ^ X(j).  Full tiles only.
+template <typename T, int VMAX, int NT>
+struct TileDma {
+  static constexpr int EPS = 16 / (2 * (int)sizeof(T));
+  static constexpr int SLOTS = (1 << VMAX) / EPS;
+  static constexpr int ITERS = SLOTS / NT;
+  static_assert(SLOTS % NT == 0, "whole waves per LDS row");
+  uint64_t off[ITERS];
+
+  template <typename G>
+  __device__ inline void init(const G& g, int tid) {
+#pragma unroll
+    for (int it = 0; it < ITERS; ++it) {
+      const uint32_t j = (uint32_t)((it * NT + tid) * EPS);
+      const uint32_t e = j ^ swz(j, g);
+      uint64_t o = 0;
+      for (int b = 0; b < VMAX; ++b) o |= (uint64_t)((e >> b) & 1u) << g.vpos[b];
+      off[it] = o;
+    }
+  }
+  __device__ inline void load(const T* rho, uint64_t base, u32x4* buf, int tid, int wave) const {
+#pragma unroll
+    for (int it = 0; it < ITERS; ++it)
+      __builtin_amdgcn_global_load_lds(rho + 2 * (base + off[it]), buf + it * NT + wave * 64, 16, 0, 0);
+  }
+  __device__ inline void store(T* rho, uint64_t base, const u32x4* buf, int tid) const {
+#pragma unroll
+    for (int it = 0; it < ITERS; ++it) *reinterpret_cast<u32x4*>(rho + 2 * (base + off[it])) = buf[it * NT + tid];
+  }
+};
+
 // ------------------------------------------------------------------------------------
 // k = 2: real-block form.  Interleaved data is a real vector of length 32 and S the 32 x 32
 // real matrix [[Sr, -Si], [Si, Sr]] (interleaved); each wave owns 16-group column blocks and
@@ -162,7 +223,7 @@ struct Op2 {
     }
   }
 
-  template <bool FULL, typename G>
+  template <bool FULL, bool RAW = false, typename G>
   __device__ inline void compute(T* ldsT, const G& g, int lane, int wave) const {
     const int cc = (lane >> 4) & 1;  // re / im of the B row
 #pragma unroll
@@ -254,7 +315,7 @@ struct Op3 {
     }
   }
 
-  template <bool FULL, typename G>
+  template <bool FULL, bool RAW = false, typename G>
   __device__ inline void compute(c2* ldsC, const G& g, int lane, int wave) const {
     const int part = wave >> 2;
     acc_t p1[NBW], p2[NBW], p3[NBW];
@@ -277,7 +338,7 @@ struct Op3 {
         }
       }
     }
-    lds_barrier();  // every wave has read the whole tile before outputs overwrite it
+    tile_barrier<RAW>();  // every wave has read the whole tile before outputs overwrite it
 #pragma unroll
     for (int i = 0; i < NBW; ++i) {
       if ((FULL || part + i * NPART < nblk) && act[i]) {

@@ -58,7 +58,8 @@ class TanqError(RuntimeError):
 
 
 class Variant(ctypes.Structure):
-    _fields_ = [("k", ctypes.c_int), ("prec", ctypes.c_int), ("tile_bits", ctypes.c_int), ("threads", ctypes.c_int)]
+    _fields_ = [("k", ctypes.c_int), ("prec", ctypes.c_int), ("tile_bits", ctypes.c_int), ("threads", ctypes.c_int),
+                ("staging", ctypes.c_int)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -351,7 +352,7 @@ def tanq_variant_count(k: int, prec: int) -> int:
 def tanq_variant_get(k: int, prec: int, index: int) -> dict:
     v = Variant()
     _check(load().tanq_variant_get(k, prec, index, ctypes.byref(v)))
-    return {"k": v.k, "prec": v.prec, "tile_bits": v.tile_bits, "threads": v.threads}
+    return {"k": v.k, "prec": v.prec, "tile_bits": v.tile_bits, "threads": v.threads, "staging": v.staging}
 
 
 def tanq_variant_select(k: int, prec: int, index: int):

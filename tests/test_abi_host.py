@@ -121,19 +121,21 @@ def test_tuning_cache_roundtrip(lib):
     P = T.TANQ_F32
     vs = [T.tanq_variant_get(3, P, i) for i in range(T.tanq_variant_count(3, P))]
     last = vs[-1]
-    text = "# cache\n\ntune 12 3 f32 %d %d 1.25\ntune 12 1 f32 0 0 0.5\n" % (last["tile_bits"], last["threads"])
+    text = "# cache\n\ntune 12 3 f32 %d %d %d 1.25\ntune 12 1 f32 0 0 0 0.5\n" % (
+        last["tile_bits"], last["threads"], last["staging"])
     T.tanq_tuning_import(text)
     try:
         assert T.tanq_variant_for(12, 3, "f32") == len(vs) - 1
         assert T.tanq_variant_for(11, 3, "f32") == T.tanq_variant_selected(3, P)
         out = T.tanq_tuning_export()
-        assert "tune 12 3 f32 %d %d 1.25\n" % (last["tile_bits"], last["threads"]) in out
-        assert "tune 12 1 f32 0 0 0.5\n" in out
+        assert "tune 12 3 f32 %d %d %d 1.25\n" % (last["tile_bits"], last["threads"], last["staging"]) in out
+        assert "tune 12 1 f32 0 0 0 0.5\n" in out
         # all-or-nothing: a bad line anywhere leaves the tables unchanged
-        for bad in ("tune 12 3 f32 99 64 1.0\n", "tune 12 3 f16 12 512 1.0\n", "tune 40 2 f64 10 256 1.0\n",
-                    "tune 12 2 f64 10 256\n", "tune 2 3 f64 12 512 1.0\n"):
+        for bad in ("tune 12 3 f32 99 64 0 1.0\n", "tune 12 3 f16 12 512 0 1.0\n", "tune 40 2 f64 10 256 0 1.0\n",
+                    "tune 12 2 f64 10 256 0\n", "tune 2 3 f64 12 512 0 1.0\n", "tune 12 2 f64 10 256 7 1.0\n"):
             with pytest.raises(T.TanqError):
-                T.tanq_tuning_import("tune 13 3 f32 %d %d 2.0\n" % (vs[0]["tile_bits"], vs[0]["threads"]) + bad)
+                T.tanq_tuning_import("tune 13 3 f32 %d %d %d 2.0\n" % (vs[0]["tile_bits"], vs[0]["threads"],
+                                                                        vs[0]["staging"]) + bad)
             assert "tune 13 3" not in T.tanq_tuning_export()
         T.tanq_variant_select(3, P, 0)  # explicit choice clears the tuned entry
         assert T.tanq_variant_for(12, 3, "f32") == 0
