@@ -73,3 +73,42 @@ def test_variant_matches_oracle(oracle_mod, k, prec, v):
                     assert rel <= 2e-6, (err, rel)
     finally:
         T.tanq_variant_select(k, P, 0)
+
+
+@pytest.mark.parametrize("k,prec,v", cases())
+def test_variant_full_size_sampled(oracle_mod, k, prec, v):
+    """At 16 qubits (64 GiB FP64 / 32 GiB FP32, the benchmark's launch shapes): one apply on a
+    seeded pseudo-random vec(rho), sampled output groups recomputed by the oracle on the
+    2^k x 2^k block each forms."""
+    n = 16
+    P = T._prec(prec)
+    desc = T.tanq_variant_get(k, P, v)
+    rng = np.random.default_rng(7 + 100 * k + 10 * v)
+    qsets = [tuple(int(x) for x in rng.choice(n, k, replace=False)), tuple(range(n - k, n))]
+    try:
+        T.tanq_variant_select(k, P, v)
+        with T.DM(n, prec) as d:
+            for qs in qsets:
+                say("n=16 variant k=%d %s tile_bits=%d threads=%d staging=%d qubits=%s"
+                    % (k, prec, desc["tile_bits"], desc["threads"], desc["staging"], qs))
+                mats = [rng.standard_normal((1 << k, 1 << k)) + 1j * rng.standard_normal((1 << k, 1 << k))
+                        for _ in range(2)]
+                op = W.channel([m * 0.4 for m in mats], qs)
+                seed = 11 + v
+                d.fill_random(seed)
+                d.apply_superop(qs, superop_of(op))
+                frees = [q for q in range(n) if q not in qs]
+                for _ in range(8):
+                    rf = sum(int(rng.integers(0, 2)) << q for q in frees)
+                    cf = sum(int(rng.integers(0, 2)) << q for q in frees)
+                    vals = (lambda idx: W.hash_fill_values(seed, idx)) if prec == "f64" else \
+                        (lambda idx: W.hash_fill_values(seed, idx).astype(np.complex64).astype(np.complex128))
+                    Q, _, M_out = oracle_mod.sample_block(vals, n, [op], rf, cf)
+                    dep = np.array([sum(((a >> t) & 1) << Q[t] for t in range(k)) for a in range(1 << k)],
+                                   dtype=np.uint64)
+                    idx = (np.uint64(rf) + dep)[:, None] + ((np.uint64(cf) + dep)[None, :] << np.uint64(n))
+                    got = d.gather(idx.reshape(-1)).astype(np.complex128).reshape(1 << k, 1 << k)
+                    tol = 1e-12 if prec == "f64" else 2e-5
+                    assert np.abs(got - M_out).max() <= tol * max(1.0, np.abs(M_out).max()), (qs, rf, cf)
+    finally:
+        T.tanq_variant_select(k, P, 0)
