@@ -106,7 +106,7 @@ def run_precision(T, torch, n, ops, prec, width, steps, warmup):
     circ = T.Circuit(n, ops)
     d = T.DM(n, prec, stream)
     t0 = time.perf_counter()
-    tuned_ms = d.autotune(reps=2)
+    tuned_ms = d.autotune(reps=2, dense=True)  # dense data: the matrix units' real clock
     d.reset()
     variants = {k: T.tanq_variant_get(k, T._prec(prec), T.tanq_variant_for(n, k, prec))
                 for k in (2, 3) if k <= n}

@@ -218,6 +218,13 @@ tanq_status tanq_variant_selected(int k, tanq_prec p, int* index);
  * k > n).  Synchronises. */
 tanq_status tanq_autotune(tanq_dm d, int reps, double* ms_per_apply);
 
+/* As tanq_autotune, but timed on dense data: d is first overwritten with the seeded
+ * pseudo-random values of tanq_dm_fill_random (seed 1) and the applies use a fixed dense
+ * unitary superoperator instead of the identity.  Dense operands draw more power in the
+ * matrix units than a mostly-zero state does, so these costs are the ones real circuits see.
+ * d's contents are replaced (call tanq_dm_reset afterwards).  Synchronises. */
+tanq_status tanq_autotune_dense(tanq_dm d, int reps, double* ms_per_apply);
+
 /* The variant applies of width k on n-qubit states use (the autotuned one, else the
  * process-wide choice). */
 tanq_status tanq_variant_for(int n, int k, tanq_prec p, int* index);

@@ -1,6 +1,8 @@
 // C ABI of libtanq (declared in include/tanq.h): handles, circuits, fusion and
 // measurement entry points.  Every compute step runs in the HIP kernels of kernels.hip;
 // this file validates arguments, owns memory and orders work on the handle's stream.
+#include <complex>
+#include <cmath>
 #include <cstdio>
 #include <mutex>
 #include <algorithm>
@@ -725,23 +727,63 @@ tanq_status tanq_tuning_import(const char* text) {
   });
 }
 
-tanq_status tanq_autotune(tanq_dm d, int reps, double* ms_per_apply) {
-  return guarded([&] {
-    check_dm(d);
-    if (reps < 1) fail(TANQ_E_ARG, "reps must be >= 1");
-    DeviceGuard g(d->device);
-    const int n = d->n;
-    const tanq_prec p = d->prec;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    TANQ_HIP(hipEventCreate(&e0));
-    TANQ_HIP(hipEventCreate(&e1));
-    double best_ms[4] = {0, 0, 0, 0};
-    try {
+// A fixed pseudo-random 2^k x 2^k unitary (Gram-Schmidt on SplitMix64-seeded entries) and its
+// superoperator conj(U) (x) U, local index row + 2^k col, row-major interleaved.
+static std::vector<double> dense_unitary_superop(int k) {
+  const int d = 1 << k, D = d * d;
+  std::vector<std::complex<double>> U((size_t)d * d);
+  uint64_t st = 0x5eed0000ull + (uint64_t)k;
+  auto next = [&st]() {
+    uint64_t z = (st += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return (double)(z >> 11) * 0x1.0p-53 - 0.5;
+  };
+  for (auto& u : U) u = {next(), next()};
+  for (int c = 0; c < d; ++c) {  // orthonormalise the columns
+    for (int b = 0; b < c; ++b) {
+      std::complex<double> dot = 0;
+      for (int r = 0; r < d; ++r) dot += std::conj(U[(size_t)r * d + b]) * U[(size_t)r * d + c];
+      for (int r = 0; r < d; ++r) U[(size_t)r * d + c] -= dot * U[(size_t)r * d + b];
+    }
+    double nrm = 0;
+    for (int r = 0; r < d; ++r) nrm += std::norm(U[(size_t)r * d + c]);
+    nrm = std::sqrt(nrm);
+    for (int r = 0; r < d; ++r) U[(size_t)r * d + c] /= nrm;
+  }
+  std::vector<double> S((size_t)D * D * 2);
+  for (int i = 0; i < D; ++i)
+    for (int j = 0; j < D; ++j) {
+      // S[(r1 + d c1), (r2 + d c2)] = conj(U[c1][c2]) U[r1][r2]
+      const int r1 = i % d, c1 = i / d, r2 = j % d, c2 = j / d;
+      const std::complex<double> v = std::conj(U[(size_t)c1 * d + c2]) * U[(size_t)r1 * d + r2];
+      S[2 * ((size_t)i * D + j)] = v.real();
+      S[2 * ((size_t)i * D + j) + 1] = v.imag();
+    }
+  return S;
+}
+
+static void autotune_impl(tanq_dm d, int reps, bool dense, double* ms_per_apply) {
+  check_dm(d);
+  if (reps < 1) fail(TANQ_E_ARG, "reps must be >= 1");
+  DeviceGuard g(d->device);
+  const int n = d->n;
+  const tanq_prec p = d->prec;
+  if (dense) launch_fill_random(d->ptr, n, p, 1, d->stream);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  TANQ_HIP(hipEventCreate(&e0));
+  TANQ_HIP(hipEventCreate(&e1));
+  double best_ms[4] = {0, 0, 0, 0};
+  try {
       for (int k = 1; k <= std::min(3, n); ++k) {
-        // identity superoperator, packed for this precision in slot 0 of the handle
+        // identity (or dense unitary) superoperator, packed in slot 0 of the handle
         const int D = 1 << (2 * k);
         std::vector<double> S((size_t)D * D * 2, 0.0);
-        for (int a = 0; a < D; ++a) S[2 * ((size_t)a * D + a)] = 1.0;
+        if (dense)
+          S = dense_unitary_superop(k);
+        else
+          for (int a = 0; a < D; ++a) S[2 * ((size_t)a * D + a)] = 1.0;
         double* raw = d->s_raw_dev;
         unsigned char* packed = d->s_packed_dev;
         TANQ_HIP(hipStreamSynchronize(d->stream));
@@ -782,16 +824,23 @@ tanq_status tanq_autotune(tanq_dm d, int reps, double* ms_per_apply) {
         best_ms[k] = best_t;
         cost_set(n, p, k, best_t);
       }
-    } catch (...) {
-      (void)hipEventDestroy(e0);
-      (void)hipEventDestroy(e1);
-      throw;
-    }
+  } catch (...) {
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    if (ms_per_apply)
-      for (int k = 0; k < 4; ++k) ms_per_apply[k] = best_ms[k];
-  });
+    throw;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (ms_per_apply)
+    for (int k = 0; k < 4; ++k) ms_per_apply[k] = best_ms[k];
+}
+
+tanq_status tanq_autotune(tanq_dm d, int reps, double* ms_per_apply) {
+  return guarded([&] { autotune_impl(d, reps, false, ms_per_apply); });
+}
+
+tanq_status tanq_autotune_dense(tanq_dm d, int reps, double* ms_per_apply) {
+  return guarded([&] { autotune_impl(d, reps, true, ms_per_apply); });
 }
 
 // ---------------------------------------------------------------------------------------

@@ -41,7 +41,7 @@ EXPORTED = [
     "tanq_fuse", "tanq_fuse_plan", "tanq_fused_info", "tanq_fused_free", "tanq_fused_get",
     "tanq_apply_superop", "tanq_apply_fused", "tanq_apply_fused_range",
     "tanq_variant_count", "tanq_variant_get", "tanq_variant_select", "tanq_variant_selected", "tanq_autotune",
-    "tanq_variant_for", "tanq_tuning_export", "tanq_tuning_import",
+    "tanq_variant_for", "tanq_tuning_export", "tanq_tuning_import", "tanq_autotune_dense",
     "tanq_probs", "tanq_probs_readout", "tanq_sample", "tanq_dm_set_basis", "tanq_reduced_dm",
     "tanq_process_chi_1q",
     "tanq_expect_pauli", "tanq_expect_pauli_c", "tanq_expect_pauli_batch",
@@ -134,6 +134,7 @@ _SIGS = {
     "tanq_probs_readout": ([_vp, _dp, _dp, _dp], ctypes.c_int),
     "tanq_dm_set_basis": ([_vp, ctypes.c_uint64, ctypes.c_uint64], ctypes.c_int),
     "tanq_variant_for": ([ctypes.c_int, ctypes.c_int, ctypes.c_int, _ip], ctypes.c_int),
+    "tanq_autotune_dense": ([_vp, ctypes.c_int, _dp], ctypes.c_int),
     "tanq_tuning_export": ([ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "tanq_tuning_import": ([ctypes.c_char_p], ctypes.c_int),
     "tanq_reduced_dm": ([_vp, ctypes.c_int, _ip, _dp], ctypes.c_int),
@@ -371,6 +372,12 @@ def tanq_autotune(h: int, reps: int = 3) -> list:
     return list(ms)
 
 
+def tanq_autotune_dense(h: int, reps: int = 3) -> list:
+    ms = (ctypes.c_double * 4)()
+    _check(load().tanq_autotune_dense(h, reps, ms))
+    return list(ms)
+
+
 def tanq_probs(h: int, dim: int, renormalize: bool = True):
     out = np.empty(dim, dtype=np.float64)
     tr = ctypes.c_double()
@@ -599,8 +606,10 @@ class DM:
     def compare(self, other: "DM"):
         return tanq_dm_compare(self.h, other.h)
 
-    def autotune(self, reps: int = 3) -> list:
-        return tanq_autotune(self.h, reps)
+    def autotune(self, reps: int = 3, dense: bool = False) -> list:
+        """Tune the apply variants on this state; dense=True overwrites it with pseudo-random
+        values and times a dense superoperator (the costs real circuits see)."""
+        return tanq_autotune_dense(self.h, reps) if dense else tanq_autotune(self.h, reps)
 
     def probs_readout(self, p01, p10) -> np.ndarray:
         return tanq_probs_readout(self.h, self.n, p01, p10)

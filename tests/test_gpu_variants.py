@@ -112,3 +112,24 @@ def test_variant_full_size_sampled(oracle_mod, k, prec, v):
                     assert np.abs(got - M_out).max() <= tol * max(1.0, np.abs(M_out).max()), (qs, rf, cf)
     finally:
         T.tanq_variant_select(k, P, 0)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_dense_autotune_records_costs(prec):
+    """Dense autotuning: every width gets a cost and a tuned variant for this n; the state it
+    leaves stays finite (a unitary applied to bounded data) and reset restores |0><0|."""
+    n = 8
+    P = T._prec(prec)
+    say("dense autotune %s n=%d" % (prec, n))
+    with T.DM(n, prec) as d:
+        ms = d.autotune(reps=1, dense=True)
+        assert all(m > 0 for m in ms[1:4])
+        for k in (2, 3):
+            assert 0 <= T.tanq_variant_for(n, k, prec) < T.tanq_variant_count(k, P)
+        v = d.read()
+        assert np.all(np.isfinite(v.view(np.float64 if prec == "f64" else np.float32)))
+        d.reset()
+        v = d.read()
+        assert v[0] == 1 and np.count_nonzero(v) == 1
+    for k in (2, 3):
+        T.tanq_variant_select(k, P, 0)  # clear the tuned entries for later tests
