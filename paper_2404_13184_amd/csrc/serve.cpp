@@ -104,6 +104,7 @@ struct ServeRequest {
   std::vector<size_t> pack_off;  // per fused block (absolute arena offsets)
   std::vector<ApplyGeom> geom;   // per fused block
   size_t cursor = 0;
+  bool finishing = false;  // its reductions are queued; leaves the resident set
   FuseLayout layout;  // planned at submit (exact footprint); consumed at admission
   // results
   double trace = 0.0;
@@ -315,6 +316,12 @@ void tanq_server_s::run_iteration() {
     }
     rr_next = (rr_next + cohort.size()) % active.size();
   }
+  // a circuit with no operations has nothing to apply: its outputs are those of |0..0><0..0|
+  for (ServeRequest* r : cohort)
+    if (r->geom.empty() && !r->finishing) {
+      r->finishing = true;
+      done_now.push_back(r);
+    }
   for (int s = 0; s < S; ++s) {
     uint32_t ni = 0, nc = 0;
     BatchItem* items = step_items(W, s);
@@ -338,7 +345,10 @@ void tanq_server_s::run_iteration() {
       }
       ++ni;
       r->cursor += 1;
-      if (r->cursor == r->geom.size()) done_now.push_back(r);
+      if (r->cursor == r->geom.size()) {
+        r->finishing = true;
+        done_now.push_back(r);
+      }
     }
     *step_count(W, s) = nc;
     if (nc) ++n_steps;
@@ -374,8 +384,7 @@ void tanq_server_s::run_iteration() {
     hipEvent_t ev = get_event();
     TANQ_HIP(hipEventRecord(ev, stream));
     finishing.push_back({ev, done_now});
-    active.erase(std::remove_if(active.begin(), active.end(),
-                                [](ServeRequest* r) { return r->cursor == r->geom.size(); }),
+    active.erase(std::remove_if(active.begin(), active.end(), [](ServeRequest* r) { return r->finishing; }),
                  active.end());
   }
 }

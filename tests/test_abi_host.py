@@ -141,3 +141,11 @@ def test_tuning_cache_roundtrip(lib):
         assert T.tanq_variant_for(12, 3, "f32") == 0
     finally:
         T.tanq_variant_select(3, P, 0)
+
+
+def test_empty_circuit_plans_no_blocks(lib):
+    c = T.Circuit(4)
+    for mode in (T.TANQ_FUSE_NONE, T.TANQ_FUSE_PAPER, 1, 2, 3):
+        blocks, nb = c.plan(mode)
+        assert nb == 0 and blocks == []
+    c.free()

@@ -360,3 +360,18 @@ def test_dm_compare(oracle_mod, pa, pb):
     assert abs(fro - np.linalg.norm(va - vb)) <= 1e-12 * np.linalg.norm(va - vb)
     assert abs(mx - np.abs(va - vb).max()) <= 1e-15
     assert abs(nrm - np.linalg.norm(va)) <= 1e-12 * np.linalg.norm(va)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_empty_circuit(prec):
+    """Fusing a circuit with no operations gives no blocks; applying it leaves |0><0|."""
+    say("empty circuit %s" % prec)
+    c = T.Circuit(5)
+    f = c.fuse(T.TANQ_FUSE_AUTO, prec)
+    assert f.count == 0 and f.info["source_ops"] == 0
+    with T.DM(5, prec) as d:
+        d.apply_fused(f)
+        p, tr = d.probs()
+        assert tr == 1.0 and p[0] == 1.0 and np.count_nonzero(p) == 1
+    f.free()
+    c.free()

@@ -121,3 +121,31 @@ def test_arrivals_while_busy_overlap():
     # some request of the second wave was admitted before the last of the first wave finished
     last_first_done = max(r["t_done"] for r in res[:8])
     assert min(r["t_admit"] for r in res[8:]) < last_first_done
+
+
+@pytest.mark.parametrize("cohort", [0, 1 * MiB])
+def test_empty_circuit_request_completes(cohort):
+    """A request with no operations finishes with the outputs of |0..0><0..0|, alone and
+    between ordinary requests (it must not wait for a superoperator that never comes)."""
+    reqs = small_requests(6, seed=91)
+    say("empty-circuit request, cohort=%d" % cohort)
+    with T.Server(256 * MiB, max_slots=8, prec="f32", width=3, steps_per_launch=4, cohort_bytes=cohort) as srv:
+        t_empty = srv.submit(5, [], probs=True, paulis=["ZIIII", "XIIII"])
+        tickets = [srv.submit(n, ops, probs=True) for n, ops, _ in reqs]
+        t_empty2 = srv.submit(4, [], probs=True)
+        for t in (t_empty, t_empty2):
+            res = srv.wait(t)
+            assert res["status"] == T.TANQ_OK and res["fused_applies"] == 0
+            p = res["probs"]
+            assert p[0] == 1.0 and np.count_nonzero(p) == 1 and res["trace"] == 1.0
+        assert list(srv.wait(t_empty)["pauli"]) == [1.0, 0.0]
+        for t in tickets:
+            assert srv.wait(t)["status"] == T.TANQ_OK
+        assert srv.stats()["completed"] == len(reqs) + 2
+
+
+def test_request_size_limits():
+    with T.Server(256 * MiB, max_slots=4, prec="f32", width=3) as srv:
+        for n in (2, 15):  # below the fusion width, above the serving limit
+            with pytest.raises(T.TanqError):
+                srv.submit(n, [W.gate(W.hadamard(), (0,))])
