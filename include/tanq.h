@@ -364,7 +364,7 @@ tanq_status tanq_server_create(const tanq_server_config* cfg, tanq_server* out);
 /* Queue a circuit (copied; c may be freed afterwards) with the outputs wanted.  Never blocks on
  * the GPU: plans the fusion on the calling thread and returns a ticket.  TANQ_E_ARG if n is
  * outside [width, 14]; TANQ_E_OOM if the request alone exceeds the budget (it could never be
- * admitted). */
+ * admitted).  A circuit with no operations completes with the outputs of |0..0><0..0|. */
 tanq_status tanq_server_submit(tanq_server s, tanq_circuit c, const tanq_outputs* outs, uint64_t* ticket);
 
 /* Result of a finished request (TANQ_E_AGAIN while it is not finished); wait blocks. */

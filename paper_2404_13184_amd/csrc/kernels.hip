@@ -85,27 +85,64 @@ __global__ void build_superops_kernel(const FuseOpDev* __restrict__ ops, const d
   }
 }
 
+// M <- S_op M for an operation on j = log4(DJ) <= 2 qubits: it mixes only the DJ rows of M that
+// differ in its target bits, so each thread owns such groups of one column and rewrites them
+// in place from registers.
+template <int DJ>
+__device__ inline void compose_groups(f64x2* M, const f64x2* Sl, const uint32_t* dep, int Dk, uint32_t tmask) {
+  const uint32_t freemask = (uint32_t)(Dk - 1) & ~tmask;
+  const int ngroups = Dk * (Dk / DJ);
+  for (int gi = threadIdx.x; gi < ngroups; gi += blockDim.x) {
+    const int c = gi % Dk;
+    uint32_t a0 = 0, rb = (uint32_t)(gi / Dk);
+    for (uint32_t m = freemask; m; m &= m - 1) {  // deposit rb into the non-target bits
+      if (rb & 1u) a0 |= m & (0u - m);
+      rb >>= 1;
+    }
+    f64x2 x[DJ];
+#pragma unroll
+    for (int b = 0; b < DJ; ++b) x[b] = M[(a0 | dep[b]) * Dk + c];
+#pragma unroll 1
+    for (int a = 0; a < DJ; ++a) {
+      double sr = 0.0, si = 0.0;
+#pragma unroll
+      for (int b = 0; b < DJ; ++b) {
+        const f64x2 w = Sl[a * DJ + b];
+        sr += w[0] * x[b][0] - w[1] * x[b][1];
+        si += w[0] * x[b][1] + w[1] * x[b][0];
+      }
+      M[(a0 | dep[a]) * Dk + c] = f64x2{sr, si};
+    }
+  }
+}
+
 // One workgroup per block: M <- S_op(embedded) M for each operation, starting from M = I.
 // Column c of the result is vec of the block's action on the basis operator with vec
-// index c, so the final M is S_blk = S_last ... S_first.
+// index c, so the final M is S_blk = S_last ... S_first.  M stays in LDS (one buffer, updated
+// in place).  Operations on one or two qubits update row groups in place (compose_groups);
+// a three-qubit operation mixes whole columns, so each thread computes its outputs into
+// registers (superoperator read from global memory) and writes them after a barrier.
 template <int KMAX>
 __global__ __launch_bounds__(256) void compose_kernel(const FuseBlockDev* __restrict__ blocks,
                                                       const FuseOpDev* __restrict__ ops,
                                                       const double* __restrict__ sops, double* __restrict__ out) {
   constexpr int DMAX = 1 << (2 * KMAX);
-  __shared__ f64x2 buf[2][DMAX * DMAX];
+  constexpr int OUT_PER_THREAD = (DMAX * DMAX + 255) / 256;
+  __shared__ f64x2 M[DMAX * DMAX];
+  __shared__ f64x2 Sl[16 * 16];
   __shared__ uint32_t dep[64];
   const FuseBlockDev blk = blocks[blockIdx.x];
   const int k = blk.k, Dk = 1 << (2 * k);
-  f64x2* Min = buf[0];
-  f64x2* Mout = buf[1];
-  for (int e = threadIdx.x; e < Dk * Dk; e += blockDim.x) Min[e] = f64x2{(e / Dk) == (e % Dk) ? 1.0 : 0.0, 0.0};
-  __syncthreads();
+  for (int e = threadIdx.x; e < Dk * Dk; e += blockDim.x) M[e] = f64x2{(e / Dk) == (e % Dk) ? 1.0 : 0.0, 0.0};
   for (int oi = 0; oi < blk.op_count; ++oi) {
     const FuseOpDev op = ops[blk.op_begin + oi];
     const int j = op.j, Dj = 1 << (2 * j);
     uint32_t tmask = 0;
     for (int t = 0; t < j; ++t) tmask |= (1u << op.pos[t]) | (1u << (k + op.pos[t]));
+    __syncthreads();  // the previous operation's reads of Sl, dep and M are done
+    const double* S = sops + 2 * op.sop_off;
+    if (j <= 2)
+      for (int e = threadIdx.x; e < Dj * Dj; e += blockDim.x) Sl[e] = f64x2{S[2 * e], S[2 * e + 1]};
     for (int b = threadIdx.x; b < Dj; b += blockDim.x) {
       uint32_t r = 0;
       for (int t = 0; t < j; ++t) {
@@ -115,33 +152,46 @@ __global__ __launch_bounds__(256) void compose_kernel(const FuseBlockDev* __rest
       dep[b] = r;
     }
     __syncthreads();
-    const double* S = sops + 2 * op.sop_off;
-    for (int e = threadIdx.x; e < Dk * Dk; e += blockDim.x) {
-      const int a = e / Dk, c = e % Dk;
-      uint32_t aloc = 0;
-      for (int t = 0; t < j; ++t) {
-        aloc |= (uint32_t)((a >> op.pos[t]) & 1) << t;
-        aloc |= (uint32_t)((a >> (k + op.pos[t])) & 1) << (j + t);
+    if (j == 1) {
+      compose_groups<4>(M, Sl, dep, Dk, tmask);
+    } else if (j == 2) {
+      compose_groups<16>(M, Sl, dep, Dk, tmask);
+    } else {
+      f64x2 y[OUT_PER_THREAD];
+#pragma unroll
+      for (int i = 0; i < OUT_PER_THREAD; ++i) {
+        const int e = threadIdx.x + i * (int)blockDim.x;
+        y[i] = f64x2{0.0, 0.0};
+        if (e >= Dk * Dk) continue;
+        const int a = e / Dk, c = e % Dk;
+        uint32_t aloc = 0;
+        for (int t = 0; t < j; ++t) {
+          aloc |= (uint32_t)((a >> op.pos[t]) & 1) << t;
+          aloc |= (uint32_t)((a >> (k + op.pos[t])) & 1) << (j + t);
+        }
+        const uint32_t abase = (uint32_t)a & ~tmask;
+        double sr = 0.0, si = 0.0;
+        for (int b = 0; b < Dj; ++b) {
+          const double wr = S[2 * (aloc * Dj + b)], wi = S[2 * (aloc * Dj + b) + 1];
+          const f64x2 v = M[(abase | dep[b]) * Dk + c];
+          sr += wr * v[0] - wi * v[1];
+          si += wr * v[1] + wi * v[0];
+        }
+        y[i] = f64x2{sr, si};
       }
-      const uint32_t abase = (uint32_t)a & ~tmask;
-      double sr = 0.0, si = 0.0;
-      for (int b = 0; b < Dj; ++b) {
-        const double xr = S[2 * (aloc * Dj + b)], xi = S[2 * (aloc * Dj + b) + 1];
-        const f64x2 y = Min[(abase | dep[b]) * Dk + c];
-        sr += xr * y[0] - xi * y[1];
-        si += xr * y[1] + xi * y[0];
+      __syncthreads();  // every read of M is done before it is overwritten
+#pragma unroll
+      for (int i = 0; i < OUT_PER_THREAD; ++i) {
+        const int e = threadIdx.x + i * (int)blockDim.x;
+        if (e < Dk * Dk) M[e] = y[i];
       }
-      Mout[e] = f64x2{sr, si};
     }
-    __syncthreads();
-    f64x2* t = Min;
-    Min = Mout;
-    Mout = t;
   }
+  __syncthreads();
   double* O = out + 2 * blk.out_off;
   for (int e = threadIdx.x; e < Dk * Dk; e += blockDim.x) {
-    O[2 * e] = Min[e][0];
-    O[2 * e + 1] = Min[e][1];
+    O[2 * e] = M[e][0];
+    O[2 * e + 1] = M[e][1];
   }
 }
 

@@ -375,3 +375,31 @@ def test_empty_circuit(prec):
         assert tr == 1.0 and p[0] == 1.0 and np.count_nonzero(p) == 1
     f.free()
     c.free()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_three_qubit_operations_fused(oracle_mod, prec):
+    """Circuits with 3-qubit gates and 3-qubit Kraus channels between 1- and 2-qubit ones,
+    fused at width 3 (the composition's whole-column path) and unfused."""
+    rng = np.random.default_rng(33)
+    n = 6
+    ops = []
+    for _ in range(6):
+        q3 = tuple(int(x) for x in rng.choice(n, 3, replace=False))
+        ops.append(W.gate(W.random_unitary(rng, 8), q3))
+        ops.append(random_channel(rng, q3))
+        q1 = int(q3[0])
+        ops.append(W.gate(W.u3(*rng.uniform(0, 6.28, 3)), (q1,)))
+        q2 = (int(q3[1]), int(q3[2]))
+        ops.append(W.gate(W.cx(), q2))
+        ops.append(W.channel(W.depolarizing(0.02, 2), q2))
+    want = oracle_mod.run(n, ops)
+    for mode in (3, T.TANQ_FUSE_NONE):
+        say("three-qubit ops %s mode=%d" % (prec, mode))
+        d = T.simulate(n, ops, mode, prec)
+        got = gpu_rho(d, oracle_mod)
+        d.free()
+        if prec == "f64":
+            check64(got, want, "mode %d" % mode)
+        else:
+            assert oracle_mod.trace_distance(got / np.trace(got), want / np.trace(want)) <= 1e-4

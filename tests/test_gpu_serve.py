@@ -109,18 +109,19 @@ def test_rejects_requests_that_never_fit():
 
 def test_arrivals_while_busy_overlap():
     """Requests submitted while others are resident join the running batch."""
-    reqs = small_requests(16, seed=12, n_range=(8, 10), depth_range=(20, 30))
+    # a first wave long enough (12 qubits, 100+ layers: hundreds of ms on the GPU) that the
+    # second wave's submissions (host-side planning of small circuits) land while it runs
+    heavy = small_requests(4, seed=12, n_range=(12, 12), depth_range=(100, 120))
+    light = small_requests(8, seed=13, n_range=(8, 10), depth_range=(20, 30))
     say("arrivals while busy")
-    with T.Server(1024 * MiB, max_slots=16, prec="f32", width=2, steps_per_launch=4) as srv:
-        first = [srv.submit(n, ops) for n, ops, _ in reqs[:8]]
-        import time
-        time.sleep(0.002)
-        second = [srv.submit(n, ops) for n, ops, _ in reqs[8:]]
+    with T.Server(2048 * MiB, max_slots=16, prec="f32", width=2, steps_per_launch=4) as srv:
+        first = [srv.submit(n, ops) for n, ops, _ in heavy]
+        second = [srv.submit(n, ops) for n, ops, _ in light]
         res = [srv.wait(t) for t in first + second]
     assert all(r["status"] == T.TANQ_OK for r in res)
     # some request of the second wave was admitted before the last of the first wave finished
-    last_first_done = max(r["t_done"] for r in res[:8])
-    assert min(r["t_admit"] for r in res[8:]) < last_first_done
+    last_first_done = max(r["t_done"] for r in res[:4])
+    assert min(r["t_admit"] for r in res[4:]) < last_first_done
 
 
 @pytest.mark.parametrize("cohort", [0, 1 * MiB])
