@@ -328,6 +328,14 @@ def main():
 
     main_prec = "f64" if "f64" in results else a.precs.split(",")[0]
     r = results[main_prec]
+    # fusion ratio (Sec. 3.3): source operations per fused apply, next to the paper's own rule
+    # (consecutive operations on the same ordered qubit tuple) planned on the host
+    cc = T.Circuit(n, ops)
+    paper_blocks = cc.plan(T.TANQ_FUSE_PAPER)[1]
+    cc.free()
+    fusion = {"source_ops": len(ops), "fused_applies": r["info"]["count"],
+              "ratio": round(len(ops) / r["info"]["count"], 2), "paper_rule_applies": paper_blocks,
+              "paper_rule_ratio": round(len(ops) / paper_blocks, 2)}
     value = r["applies"] / r["wall_s"]
 
     def dominant(rr, prec):
@@ -361,6 +369,7 @@ def main():
                    "fused_applies_per_step": r["info"]["count"], "fusion_width": r["info"]["max_width"],
                    "count_by_k": r["info"]["count_k"][1:]},
         "gates_per_s": round(len(ops) * a.steps / r["wall_s"], 1),
+        "fusion": fusion,
         "roofline": dominant(r, main_prec),
     }
     for prec, rr in results.items():
