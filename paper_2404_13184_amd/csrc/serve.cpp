@@ -460,6 +460,7 @@ void tanq_server_s::loop() {
           to_admit.push_back(r);
         }
       }
+      bool deferred = false;  // a request went back to the queue for lack of memory
       for (ServeRequest* r : to_admit) {
         size_t roff = 0;
         r->res_size = (1 + (r->want_probs ? ((size_t)1 << r->n) : 0) + 2 * r->paulis.size()) * sizeof(double);
@@ -474,7 +475,8 @@ void tanq_server_s::loop() {
           if (ok) pinned.release(roff, r->res_size);
           std::lock_guard<std::mutex> lk(mu);
           if (e.code == TANQ_E_OOM) {
-            // arena fragmentation: retry later
+            // arena fragmentation or result space held by unreleased results: retry later
+            deferred = true;
             r->state = 0;
             free_slots.push_back(r->slot);
             r->slot = -1;
@@ -491,6 +493,11 @@ void tanq_server_s::loop() {
       }
       if (!active.empty()) {
         run_iteration();
+      } else if (deferred && finishing.empty()) {
+        // nothing on the GPU will free memory: wait for a release (or new work) instead of
+        // retrying the admission in a busy loop
+        std::unique_lock<std::mutex> lk(mu);
+        cv_submit.wait_for(lk, std::chrono::milliseconds(1));
       }
       finalize_done(active.empty() && !finishing.empty());
       n_active.store((int)active.size());
