@@ -160,6 +160,8 @@ typedef struct {
  * the same n and precision.  Synchronises hip_stream before returning. */
 tanq_status tanq_fuse(tanq_circuit c, int max_width, tanq_prec p, void* hip_stream, tanq_fused* out);
 tanq_status tanq_fused_info(tanq_fused f, tanq_fused_info_t* info);
+/* Waits for all work queued on f's device (applies of f may be in flight on any stream), then
+ * releases its device memory. */
 tanq_status tanq_fused_free(tanq_fused f);
 
 /* Host-only planning query (no GPU needed): the block that each operation of c joins under

@@ -523,6 +523,8 @@ tanq_status tanq_fused_free(tanq_fused f) {
   return guarded([&] {
     if (!f) return;
     (void)hipSetDevice(f->device);
+    // applies of f may still be queued on any stream of the device
+    (void)hipDeviceSynchronize();
     dfree(f->raw);
     dfree(f->packed);
     delete f;
