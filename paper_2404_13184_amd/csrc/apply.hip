@@ -10,7 +10,9 @@
 // 2^(V-2k) elements.  Tiles move with 16-byte per-lane accesses (coalesced) through LDS; the
 // grid is persistent; the next tile is prefetched into registers while the current one is
 // multiplied, and the loop is rotated so that waiting for that prefetch never waits for the
-// previous tile's stores.
+// previous tile's stores.  Barriers fence LDS only, so global loads and stores stay in flight
+// across them.  A second staging mode (apply_dma_kernel) streams the next tile straight into
+// a second LDS buffer with global-to-LDS loads instead of through registers.
 //
 // LDS swizzle.  Element e of a tile lives at LDS element e ^ X(e), where X copies up to four
 // group-index bits that lie above the 256-byte bank window into target-bit positions inside
