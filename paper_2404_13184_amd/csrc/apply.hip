@@ -61,7 +61,7 @@ __global__ __launch_bounds__(NT) void apply_tiles_kernel(T* __restrict__ rho, co
     op.load(frag, lane, wave);
   op.prepare(g, lane, wave);
 
-  uint64_t tile = blockIdx.x;
+  uint64_t tile = xcd_first_tile();
   if (tile >= g.ntiles) return;  // uniform per workgroup
   uint64_t cur = tile_base(g, tile);
   u32x4 buf[IO::ITERS];
@@ -131,7 +131,7 @@ __global__ __launch_bounds__(NT) void apply_dma_kernel(T* __restrict__ rho, cons
     op.load(frag, lane, wave);
   op.prepare(g, lane, wave);
 
-  uint64_t tile = blockIdx.x;
+  uint64_t tile = xcd_first_tile();
   if (tile >= g.ntiles) return;  // uniform per workgroup
   uint64_t cur = tile_base(g, tile);
   io.load(rho, cur, lds[0], tid, wave);

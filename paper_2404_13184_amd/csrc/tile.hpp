@@ -94,6 +94,19 @@ struct TileIo {
   __device__ inline bool has(int it, int tid) const { return FULL || it * NT + tid < slots; }
 };
 
+// First tile of this workgroup in a persistent grid (each workgroup then advances by
+// gridDim.x).  Workgroups are dealt round-robin over the 8 XCDs; when the grid is a multiple
+// of 8, XCD x gets the contiguous range [x, x + 1) * gridDim.x / 8 of first tiles, so the tiles
+// in flight on one XCD differ in their low tile-index bits.  Otherwise the concurrent tiles of
+// an XCD share those bits (and the address bits they select), which on some qubit placements
+// confines one XCD's traffic to a fraction of its memory channels.  Any value is a bijection
+// of [0, gridDim.x), so every tile is still processed exactly once.
+__device__ inline uint64_t xcd_first_tile() {
+  const uint32_t gx = gridDim.x, bx = blockIdx.x;
+  if (gx % 8u != 0u) return bx;
+  return (uint64_t)((bx % 8u) * (gx / 8u) + bx / 8u);
+}
+
 template <typename G>
 __device__ inline uint64_t tile_base(const G& g, uint64_t tile) {
   uint64_t b = 0;
