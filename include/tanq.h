@@ -191,7 +191,8 @@ tanq_status tanq_apply_fused(tanq_dm d, tanq_fused f);
 tanq_status tanq_apply_fused_range(tanq_dm d, tanq_fused f, int begin, int end);
 
 /* ---------------------------------------------------------------------------------------
- * Autotuning of the apply kernels (tile shape and workgroup size per width and precision).
+ * Autotuning of the apply kernels (tile shape, workgroup size and staging per qubit count,
+ * width and precision).
  * ------------------------------------------------------------------------------------- */
 
 typedef struct {
@@ -206,7 +207,8 @@ typedef struct {
 /* Number of apply-kernel variants for width k (2 or 3) and precision p; k = 1 has one. */
 tanq_status tanq_variant_count(int k, tanq_prec p, int* count);
 tanq_status tanq_variant_get(int k, tanq_prec p, int index, tanq_variant_t* out);
-/* Process-wide choice used by every later apply of that width and precision. */
+/* Process-wide choice used by every later apply of that width and precision (it also clears
+ * the autotuned entries of that width and precision). */
 tanq_status tanq_variant_select(int k, tanq_prec p, int index);
 tanq_status tanq_variant_selected(int k, tanq_prec p, int* index);
 
@@ -233,8 +235,8 @@ tanq_status tanq_variant_for(int n, int k, tanq_prec p, int* index);
 
 /* The autotuning cache as text, to keep tuning results across processes: one line per tuned
  * (n, k, precision), "tune <n> <k> <f64|f32> <tile_bits> <threads> <staging> <ms per apply>"
- * (tile bits, threads and staging are 0 for k = 1).  buf may be NULL to query; *len receives the size needed,
- * including the terminating NUL; E_ARG if cap is smaller. */
+ * (tile bits, threads and staging are 0 for k = 1).  buf may be NULL to query; *len receives
+ * the size needed, including the terminating NUL; E_ARG if cap is smaller. */
 tanq_status tanq_tuning_export(char* buf, size_t cap, size_t* len);
 /* Load text written by tanq_tuning_export (blank lines and lines starting with '#' are
  * skipped).  Every line is validated first -- E_ARG names a malformed line or a variant this
