@@ -148,3 +148,28 @@ def test_block_separable_noisy_circuit(oracle_mod, mode):
     z0 = oracle_mod.expect_pauli(parts[0], "ZIII")
     z1 = oracle_mod.expect_pauli(parts[1], "ZIII")
     assert abs(zz[0] - z0 * z1) <= 1e-12
+
+
+@pytest.mark.parametrize("qubits", [(16, 3), (0, 16, 9)])
+def test_largest_register_fp32(oracle_mod, qubits):
+    """n = 17, the largest register the library accepts: 4^17 complex64 = 128 GiB, element
+    indices beyond 2^32.  One apply on a seeded fill, sampled groups against the oracle."""
+    n = 17
+    rng = np.random.default_rng(17 + len(qubits))
+    op = random_channel(rng, qubits)
+    seed = 3
+    say("n=17 f32 apply qubits=%s" % (qubits,))
+    with T.DM(n, "f32") as d:
+        d.fill_random(seed)
+        d.apply_superop(qubits, superop_of(op))
+        frees = [q for q in range(n) if q not in qubits]
+        for _ in range(12):
+            rf = sum(int(rng.integers(0, 2)) << q for q in frees)
+            cf = sum(int(rng.integers(0, 2)) << q for q in frees)
+            vals = lambda idx: W.hash_fill_values(seed, idx).astype(np.complex64).astype(np.complex128)
+            Q, _, M_out = oracle_mod.sample_block(vals, n, [op], rf, cf)
+            k = len(Q)
+            dep = np.array([sum(((a >> t) & 1) << Q[t] for t in range(k)) for a in range(1 << k)], dtype=np.uint64)
+            idx = (np.uint64(rf) + dep)[:, None] + ((np.uint64(cf) + dep)[None, :] << np.uint64(n))
+            got = d.gather(idx.reshape(-1)).astype(np.complex128).reshape(1 << k, 1 << k)
+            assert np.abs(got - M_out).max() <= 2e-5 * max(1.0, np.abs(M_out).max()), (rf, cf)
