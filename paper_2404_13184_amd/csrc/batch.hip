@@ -1,8 +1,8 @@
 // Batched superoperator apply for the serving loop (gfx950): one launch applies the next fused
 // superoperator of every active request to that request's own vec(rho).  The work is a list of
-// chunks (request item, range of tiles); a persistent grid walks the list, stages each item's
-// tile geometry in LDS and runs the same in-place tile multiplication as the single-state
-// kernels (tile.hpp).  States of different requests are disjoint, so the chunks of one launch
+// chunks (request item, range of tiles); a persistent grid claims chunks from the list one at
+// a time (an atomic counter in the work list), stages each item's tile geometry in LDS and
+// runs the same in-place tile multiplication as the single-state kernels (tile.hpp).  States of different requests are disjoint, so the chunks of one launch
 // are independent; successive launches are ordered on the stream.  The number of chunks is read
 // from device memory, which lets a fixed launch be captured in a graph and replayed.
 #include <type_traits>
@@ -58,7 +58,7 @@ __device__ inline void batch_tiles(T* __restrict__ rho, const IO& io, const Op& 
 template <typename T, int K, int VMAX, int NT>
 __global__ __launch_bounds__(NT) void batch_apply_kernel(const BatchItem* __restrict__ items,
                                                          const BatchChunk* __restrict__ chunks,
-                                                         const uint32_t* __restrict__ count) {
+                                                         uint32_t* __restrict__ count) {
   using IO = TileIo<T, VMAX, NT>;
   using Op = std::conditional_t<K == 2, Op2<T, VMAX, NT>, Op3<T, VMAX, NT>>;
   static_assert(sizeof(ApplyGeom) % 4 == 0, "geometry copied as dwords");
@@ -69,14 +69,22 @@ __global__ __launch_bounds__(NT) void batch_apply_kernel(const BatchItem* __rest
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const uint32_t nch = *count;
+  const uint32_t nch = count[0];
+  __shared__ uint32_t s_next;
 
   uint32_t cur = 0xffffffffu;
   bool full = false;
   IO io;
   Op op;
   T* rho = nullptr;
-  for (uint32_t c = blockIdx.x; c < nch; c += gridDim.x) {
+  for (;;) {
+    // dynamic assignment: each workgroup claims the next chunk (count[1], zeroed by the copy of
+    // the work list that precedes every launch), so the launch ends when its last chunks do
+    if (tid == 0) s_next = atomicAdd(&count[1], 1u);
+    lds_barrier();
+    const uint32_t c = s_next;
+    lds_barrier();
+    if (c >= nch) break;
     const BatchChunk ch = chunks[c];
     if (ch.item != cur) {
       lds_barrier();  // the previous item's geometry is no longer read
@@ -123,7 +131,7 @@ int batch_tile_bits(int k, tanq_prec p) {
 }
 
 template <typename T, int K>
-static void launch_batch_typed(const BatchItem* items, const BatchChunk* chunks, const uint32_t* count,
+static void launch_batch_typed(const BatchItem* items, const BatchChunk* chunks, uint32_t* count,
                                hipStream_t s) {
   constexpr int V = BatchShape<T, K>::V, NT = BatchShape<T, K>::NT;
   auto kern = batch_apply_kernel<T, K, V, NT>;
@@ -141,7 +149,7 @@ static void launch_batch_typed(const BatchItem* items, const BatchChunk* chunks,
   TANQ_HIP(hipGetLastError());
 }
 
-void launch_batch(int k, tanq_prec p, const BatchItem* items, const BatchChunk* chunks, const uint32_t* count,
+void launch_batch(int k, tanq_prec p, const BatchItem* items, const BatchChunk* chunks, uint32_t* count,
                   hipStream_t s) {
   if (k == 2) {
     if (p == TANQ_F64) launch_batch_typed<double, 2>(items, chunks, count, s);

@@ -171,7 +171,7 @@ int device_cu_count();
 int batch_tile_bits(int k, tanq_prec p);
 // Apply the items of `*count` chunks (count lives in device memory so the launch can be
 // captured in a graph and replayed with new contents).
-void launch_batch(int k, tanq_prec p, const BatchItem* items, const BatchChunk* chunks, const uint32_t* count,
+void launch_batch(int k, tanq_prec p, const BatchItem* items, const BatchChunk* chunks, uint32_t* count,
                   hipStream_t s);
 
 }  // namespace tanq

@@ -204,7 +204,8 @@ struct tanq_server_s {
   }
   void put_event(hipEvent_t e) { event_pool.push_back(e); }
 
-  // Work buffer layout per step s: [count u32 (padded to 256)] [items] [chunks]
+  // Work buffer layout per step s: [chunk count u32, next-chunk counter u32 (padded to 256)]
+  // [items] [chunks]
   size_t step_bytes() const {
     return 256 + align256(items_per_step * sizeof(BatchItem)) + align256(chunks_per_step * sizeof(BatchChunk));
   }
@@ -350,7 +351,8 @@ void tanq_server_s::run_iteration() {
         done_now.push_back(r);
       }
     }
-    *step_count(W, s) = nc;
+    step_count(W, s)[0] = nc;
+    step_count(W, s)[1] = 0;  // next unclaimed chunk, reset by the copy before each launch
     if (nc) ++n_steps;
   }
   if (graph[b]) {
