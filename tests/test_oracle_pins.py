@@ -412,6 +412,35 @@ def test_diag_and_trace(oracle_mod):
     assert abs(tr - 1) <= TOL and np.abs(p - np.diag(rho).real).max() == 0
 
 
+def test_trace_distance_closed_forms(oracle_mod):
+    """Orthogonal pure states are at distance 1, |0><0| is 1/2 from I/2, and two pure states
+    are sqrt(1 - |<a|b>|^2) apart (the Fuchs-van de Graaf equality for pure states)."""
+    z = np.diag([1.0, 0.0]).astype(complex)
+    o = np.diag([0.0, 1.0]).astype(complex)
+    assert abs(oracle_mod.trace_distance(z, o) - 1.0) <= 1e-15
+    assert abs(oracle_mod.trace_distance(z, np.eye(2) / 2) - 0.5) <= 1e-15
+    rng = np.random.default_rng(9)
+    for _ in range(5):
+        a = rng.normal(size=8) + 1j * rng.normal(size=8)
+        b = rng.normal(size=8) + 1j * rng.normal(size=8)
+        a /= np.linalg.norm(a)
+        b /= np.linalg.norm(b)
+        want = math.sqrt(max(0.0, 1.0 - abs(np.vdot(a, b)) ** 2))
+        got = oracle_mod.trace_distance(np.outer(a, a.conj()), np.outer(b, b.conj()))
+        assert abs(got - want) <= 1e-12
+
+
+def test_vec_layout_column_stacking(oracle_mod):
+    """vec(rho) stacks columns: element r + c 2^n holds rho[r, c] (Sec. 3.1)."""
+    n = 2
+    for r, c in [(1, 2), (3, 0), (0, 3), (2, 2)]:
+        v = np.zeros(16, dtype=complex)
+        v[r + c * 4] = 1.0
+        m = oracle_mod.vec_to_matrix(v, n)
+        assert m[r, c] == 1.0 and np.count_nonzero(m) == 1
+        assert np.array_equal(oracle_mod.matrix_to_vec(m), v)
+
+
 def test_sample_block_matches_full(oracle_mod):
     """The per-group definition used for full-size sampling agrees with a full run."""
     rng = np.random.default_rng(12)
