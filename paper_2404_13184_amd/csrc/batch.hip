@@ -130,22 +130,36 @@ int batch_tile_bits(int k, tanq_prec p) {
   return p == TANQ_F64 ? BatchShape<double, 3>::V : BatchShape<float, 3>::V;
 }
 
+// Persistent grid of the batched kernel: as many workgroups as fit on the device at once.
 template <typename T, int K>
-static void launch_batch_typed(const BatchItem* items, const BatchChunk* chunks, uint32_t* count,
-                               hipStream_t s) {
-  constexpr int V = BatchShape<T, K>::V, NT = BatchShape<T, K>::NT;
-  auto kern = batch_apply_kernel<T, K, V, NT>;
+static unsigned batch_grid_typed() {
+  constexpr int NT = BatchShape<T, K>::NT;
   static thread_local int cap_dev = -1;
   static thread_local unsigned cap = 0;
   int dev = 0;
   TANQ_HIP(hipGetDevice(&dev));
   if (cap_dev != dev) {
     int per_cu = 0;
-    TANQ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, NT, 0));
+    TANQ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, batch_apply_kernel<T, K, BatchShape<T, K>::V, NT>, NT, 0));
     cap = (unsigned)(device_cu_count() * (per_cu < 1 ? 1 : per_cu));
     cap_dev = dev;
   }
-  hipLaunchKernelGGL(kern, dim3(cap), dim3(NT), 0, s, items, chunks, count);
+  return cap;
+}
+
+int batch_grid(int k, tanq_prec p) {
+  if (k == 2) return (int)(p == TANQ_F64 ? batch_grid_typed<double, 2>() : batch_grid_typed<float, 2>());
+  if (k == 3) return (int)(p == TANQ_F64 ? batch_grid_typed<double, 3>() : batch_grid_typed<float, 3>());
+  fail(TANQ_E_ARG, "batched width must be 2 or 3");
+}
+
+template <typename T, int K>
+static void launch_batch_typed(const BatchItem* items, const BatchChunk* chunks, uint32_t* count,
+                               hipStream_t s) {
+  constexpr int V = BatchShape<T, K>::V, NT = BatchShape<T, K>::NT;
+  hipLaunchKernelGGL((batch_apply_kernel<T, K, V, NT>), dim3(batch_grid_typed<T, K>()), dim3(NT), 0, s, items,
+                     chunks, count);
   TANQ_HIP(hipGetLastError());
 }
 

@@ -169,6 +169,8 @@ int device_cu_count();
 // Tile bits of the batched kernel for width k (2 or 3) and precision p (geometry of the items
 // must be built with this value).
 int batch_tile_bits(int k, tanq_prec p);
+// Workgroups of the batched kernel's persistent grid on the current device.
+int batch_grid(int k, tanq_prec p);
 // Apply the items of `*count` chunks (count lives in device memory so the launch can be
 // captured in a graph and replayed with new contents).
 void launch_batch(int k, tanq_prec p, const BatchItem* items, const BatchChunk* chunks, uint32_t* count,

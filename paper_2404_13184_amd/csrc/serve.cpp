@@ -114,7 +114,8 @@ struct ServeRequest {
 };
 
 constexpr int kServeMaxN = 14;
-constexpr uint64_t kChunksPerItem = 256;
+constexpr uint64_t kChunksPerItem = 256;  // chunk-list capacity per slot and step
+constexpr uint64_t kMinChunkTiles = 4;    // smallest chunk (guided sizes shrink towards it)
 
 static size_t state_bytes(int n, tanq_prec p) { return ((size_t)1 << (2 * n)) * elem_size(p); }
 
@@ -149,6 +150,7 @@ struct tanq_server_s {
 
   // step work buffers (double-buffered), pinned and device, with one graph each
   size_t items_per_step = 0, chunks_per_step = 0, work_bytes = 0;
+  uint64_t grid = 1;  // workgroups of the batched kernel's persistent grid
   unsigned char* work_host[2] = {nullptr, nullptr};
   unsigned char* work_dev[2] = {nullptr, nullptr};
   hipEvent_t work_ev[2] = {nullptr, nullptr};
@@ -329,26 +331,48 @@ void tanq_server_s::run_iteration() {
     BatchChunk* chunks = step_chunks(W, s);
     for (ServeRequest* r : cohort) {
       if (r->cursor >= r->geom.size()) continue;
-      const ApplyGeom& g = r->geom[r->cursor];
       BatchItem& it = items[ni];
       it.rho = (uint64_t)(uintptr_t)(arena_base + r->rho_off);
       it.frag = (uint64_t)(uintptr_t)(arena_base + r->pack_off[r->cursor]);
-      it.g = g;
-      // at most kChunksPerItem chunks per item and at least 16 tiles per chunk
-      const uint64_t ct = std::max<uint64_t>(16, (g.ntiles + kChunksPerItem - 1) / kChunksPerItem);
-      for (uint64_t t0 = 0; t0 < g.ntiles; t0 += ct) {
-        if (nc >= chunks_per_step) fail(TANQ_E_STATE, "chunk list overflow");
-        chunks[nc].item = ni;
-        chunks[nc].tile_begin = (uint32_t)t0;
-        chunks[nc].tile_end = (uint32_t)std::min<uint64_t>(g.ntiles, t0 + ct);
-        chunks[nc].pad = 0;
-        ++nc;
-      }
+      it.g = r->geom[r->cursor];
       ++ni;
       r->cursor += 1;
       if (r->cursor == r->geom.size()) {
         r->finishing = true;
         done_now.push_back(r);
+      }
+    }
+    // Chunks, claimed in list order by the persistent grid: items by decreasing size, cut with
+    // guided sizes (remaining tiles of the step / grid size, at least kMinChunkTiles), so the
+    // first claims are long and the last ones short and the workgroups finish close together.
+    // An item boundary may cut a chunk short; a chunk never spans two items.
+    std::vector<uint32_t> order(ni);
+    std::vector<uint64_t> ntiles(ni);
+    uint64_t remaining = 0;
+    for (uint32_t i = 0; i < ni; ++i) {
+      order[i] = i;
+      ntiles[i] = items[i].g.ntiles;
+      remaining += ntiles[i];
+    }
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return ntiles[a] > ntiles[b]; });
+    for (uint32_t oi = 0; oi < ni; ++oi) {
+      const uint32_t i = order[oi];
+      const uint64_t nt = ntiles[i];
+      for (uint64_t t0 = 0; t0 < nt;) {
+        // keep room for one chunk per item still to come, whatever the sizes
+        const uint64_t later = ni - 1 - oi;
+        if ((uint64_t)nc + later >= chunks_per_step) fail(TANQ_E_STATE, "chunk list overflow");
+        const uint64_t room = chunks_per_step - nc - later;
+        uint64_t ct = std::max<uint64_t>(kMinChunkTiles, (remaining + grid - 1) / grid);
+        ct = std::max<uint64_t>(ct, (remaining + room - 1) / room);
+        ct = std::min<uint64_t>(ct, nt - t0);
+        chunks[nc].item = i;
+        chunks[nc].tile_begin = (uint32_t)t0;
+        chunks[nc].tile_end = (uint32_t)(t0 + ct);
+        chunks[nc].pad = 0;
+        ++nc;
+        t0 += ct;
+        remaining -= ct;
       }
     }
     step_count(W, s)[0] = nc;
@@ -613,6 +637,7 @@ tanq_status tanq_server_create(const tanq_server_config* cfg, tanq_server* out) 
       // chunk capacity: every slot at most kChunksPerItem chunks
       s->items_per_step = (size_t)c.max_slots;
       s->chunks_per_step = (size_t)c.max_slots * kChunksPerItem;
+      s->grid = (uint64_t)std::max(1, batch_grid(c.width, (tanq_prec)c.prec));
       s->work_bytes = s->step_bytes() * c.steps_per_launch;
       for (int b = 0; b < 2; ++b) {
         TANQ_HIP(hipHostMalloc((void**)&s->work_host[b], s->work_bytes, hipHostMallocDefault));
