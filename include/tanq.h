@@ -229,6 +229,27 @@ tanq_status tanq_autotune(tanq_dm d, int reps, double* ms_per_apply);
  * d's contents are replaced (call tanq_dm_reset afterwards).  Synchronises. */
 tanq_status tanq_autotune_dense(tanq_dm d, int reps, double* ms_per_apply);
 
+/* Multi-superoperator passes.  tanq_apply_fused and tanq_apply_fused_range apply each run of
+ * consecutive 2-qubit blocks whose qubits together number at most 6 in one pass over vec(rho):
+ * every tile of the state is read into LDS once, multiplied by each superoperator of the run in
+ * circuit order (the same per-group arithmetic as a single apply, so the results are bitwise
+ * those of applying the blocks one by one), and written back once.  This cuts HBM traffic, the
+ * bound of 2-qubit applies (Sec. 3.2: a 2-qubit superoperator is memory-bound).  A pass needs
+ * 2n >= 12 (FP64) or 13 (FP32) bits of state.  The limit is the most superoperators per pass,
+ * 1..8 (1 = no passes; default 8), process-wide. */
+tanq_status tanq_set_pass_limit(int max_superops);
+tanq_status tanq_get_pass_limit(int* max_superops);
+/* How tanq_apply_fused groups f's blocks under the current limit: *passes receives the number
+ * of multi-superoperator passes and *in_passes the blocks they apply (the other blocks are
+ * applied one by one).  Host only. */
+tanq_status tanq_fused_passes(tanq_fused f, int* passes, int* in_passes);
+/* Diagnostics of one pass layout (host only): m 2-qubit superoperators on n qubits, qubits =
+ * m pairs; *conflict_free receives how many of the 2 m LDS access patterns (the MFMA operand
+ * reads and the result writes of each superoperator) the chosen swizzle keeps free of bank
+ * conflicts.  E_ARG if the pass is not valid (qubits out of range or repeated within a block,
+ * more than 6 distinct qubits, m outside 1..8, too small a state). */
+tanq_status tanq_pass_layout_info(int n, int m, const int* qubits, tanq_prec p, int* conflict_free);
+
 /* The variant applies of width k on n-qubit states use (the autotuned one, else the
  * process-wide choice). */
 tanq_status tanq_variant_for(int n, int k, tanq_prec p, int* index);

@@ -7,6 +7,7 @@
 #include <mutex>
 #include <algorithm>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <string>
 #include <vector>
@@ -102,6 +103,9 @@ struct tanq_fused_s {
   std::vector<FusedBlockHost> blocks;
   double* raw = nullptr;
   unsigned char* packed = nullptr;
+  // pass geometries already built, by (first block, length)
+  std::mutex pass_mu;
+  std::map<std::pair<int, int>, tanq::PassGeom> passes;
 };
 
 namespace {
@@ -172,6 +176,47 @@ void parse_pauli(int n, const char* s, uint64_t out[3]) {
 }
 
 }  // namespace
+
+// Contiguous elements (log2) of a pass tile in vec(rho): the tile holds the row and column bit
+// of every qubit in `qmask` plus the lowest other bits up to V; the low run is the number of
+// consecutive held bits from bit 0.  -1 if the qubits do not fit.
+inline int pass_low_run(uint64_t qmask, int n, int V) {
+  uint64_t held = qmask | (qmask << n);
+  int fill = V - __builtin_popcountll(held);
+  if (fill < 0) return -1;
+  for (int b = 0; b < 2 * n && fill > 0; ++b)
+    if (!((held >> b) & 1ull)) {
+      held |= 1ull << b;
+      --fill;
+    }
+  int c = 0;
+  while (c < 2 * n && ((held >> c) & 1ull)) ++c;
+  return c;
+}
+
+// Length of the pass that starts at block i (blocks before `end`): the longest run of
+// consecutive 2-qubit blocks, at most `lim`, whose qubits fit one pass tile with runs of at
+// least 128 contiguous bytes in vec(rho) (whole cache lines: shorter runs make the HBM fetch
+// more than it uses); 1 when no pass applies (a different width, too small a state, passes
+// switched off).  at(j, &q) returns the width of block j and points q at its qubits.
+template <typename BlockAt>
+int pass_run(BlockAt at, int i, int end, int n, tanq_prec p, int lim) {
+  const int V = pass_tile_bits(p);
+  const int min_run = p == TANQ_F64 ? 3 : 4;  // 8 x 16 B or 16 x 8 B
+  if (lim < 2 || 2 * n < V) return 1;
+  const int* q = nullptr;
+  if (at(i, &q) != 2) return 1;
+  uint64_t mask = (1ull << q[0]) | (1ull << q[1]);
+  int m = 1;
+  while (i + m < end && m < lim) {
+    if (at(i + m, &q) != 2) break;
+    const uint64_t nm = mask | (1ull << q[0]) | (1ull << q[1]);
+    if (pass_low_run(nm, n, V) < min_run) break;
+    mask = nm;
+    ++m;
+  }
+  return m;
+}
 
 extern "C" {
 
@@ -580,9 +625,38 @@ tanq_status tanq_apply_fused_range(tanq_dm d, tanq_fused f, int begin, int end) 
     if (f->prec != d->prec) fail(TANQ_E_STATE, "fused list was packed for a different precision");
     if (begin < 0 || end > (int)f->blocks.size() || begin > end) fail(TANQ_E_ARG, "bad range");
     DeviceGuard g(d->device);
-    for (int i = begin; i < end; ++i) {
+    const int lim = pass_limit();
+    auto at = [&](int j, const int** q) {
+      *q = f->blocks[j].qubits;
+      return f->blocks[j].k;
+    };
+    for (int i = begin; i < end;) {
       const FusedBlockHost& b = f->blocks[i];
-      launch_apply(d->ptr, d->n, d->prec, b.k, b.qubits, f->packed + b.pack_off, d->stream);
+      const int m = pass_run(at, i, end, d->n, d->prec, lim);
+      if (m >= 2) {
+        const PassGeom* pg = nullptr;
+        {
+          std::lock_guard<std::mutex> lk(f->pass_mu);
+          auto it = f->passes.find({i, m});
+          if (it == f->passes.end()) {
+            int q[2 * kPassMax];
+            uint32_t off[kPassMax];
+            const size_t es = d->prec == TANQ_F64 ? sizeof(double) : sizeof(float);
+            for (int t = 0; t < m; ++t) {
+              q[2 * t] = f->blocks[i + t].qubits[0];
+              q[2 * t + 1] = f->blocks[i + t].qubits[1];
+              off[t] = (uint32_t)((f->blocks[i + t].pack_off - b.pack_off) / es);
+            }
+            it = f->passes.emplace(std::make_pair(i, m), make_pass_geom(d->n, m, q, off, d->prec)).first;
+          }
+          pg = &it->second;  // map nodes are stable; entries are never erased
+        }
+        launch_pass(d->ptr, d->prec, *pg, f->packed + b.pack_off, d->stream);
+        i += m;
+      } else {
+        launch_apply(d->ptr, d->n, d->prec, b.k, b.qubits, f->packed + b.pack_off, d->stream);
+        ++i;
+      }
     }
   });
 }
@@ -835,6 +909,52 @@ static void autotune_impl(tanq_dm d, int reps, bool dense, double* ms_per_apply)
   (void)hipEventDestroy(e1);
   if (ms_per_apply)
     for (int k = 0; k < 4; ++k) ms_per_apply[k] = best_ms[k];
+}
+
+tanq_status tanq_set_pass_limit(int max_superops) {
+  return guarded([&] { set_pass_limit(max_superops); });
+}
+
+tanq_status tanq_get_pass_limit(int* max_superops) {
+  return guarded([&] {
+    if (!max_superops) fail(TANQ_E_ARG, "max_superops is NULL");
+    *max_superops = pass_limit();
+  });
+}
+
+tanq_status tanq_fused_passes(tanq_fused f, int* passes, int* in_passes) {
+  return guarded([&] {
+    if (!f || !passes || !in_passes) fail(TANQ_E_ARG, "NULL argument");
+    const int lim = pass_limit();
+    auto at = [&](int j, const int** q) {
+      *q = f->blocks[j].qubits;
+      return f->blocks[j].k;
+    };
+    int np = 0, nin = 0;
+    const int end = (int)f->blocks.size();
+    for (int i = 0; i < end;) {
+      const int m = pass_run(at, i, end, f->n, f->prec, lim);
+      if (m >= 2) {
+        ++np;
+        nin += m;
+      }
+      i += m;
+    }
+    *passes = np;
+    *in_passes = nin;
+  });
+}
+
+tanq_status tanq_pass_layout_info(int n, int m, const int* qubits, tanq_prec p, int* conflict_free) {
+  return guarded([&] {
+    if (!qubits || !conflict_free) fail(TANQ_E_ARG, "NULL argument");
+    check_prec(p);
+    if (n < 1 || n > MAX_N) fail(TANQ_E_ARG, "n out of range");
+    uint32_t off[kPassMax] = {0};
+    int score = 0;
+    (void)make_pass_geom(n, m, qubits, off, p, &score);
+    *conflict_free = score;
+  });
 }
 
 tanq_status tanq_autotune(tanq_dm d, int reps, double* ms_per_apply) {

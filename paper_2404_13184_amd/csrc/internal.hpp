@@ -59,6 +59,27 @@ struct C1Geom {
   int32_t n;
 };
 
+// A pass: up to kPassMax consecutive 2-qubit superoperators applied to each tile while it is in
+// LDS.  The tile holds every target bit of the pass (plus the lowest other bits up to V); the
+// LDS swizzle is the linear map S(e) = e ^ (XOR of xcol[b] over the set bits b of e above the
+// 256-byte bank window).
+constexpr int kPassMax = 8;
+struct PassGeom {
+  uint64_t ntiles;               // 2^(2n - V)
+  int32_t V;                     // tile bits
+  int32_t nruns;                 // runs of fixed bits
+  int32_t m;                     // superoperators in the pass
+  int32_t pad;
+  uint32_t op_off[kPassMax];     // element offset of superoperator j's packed operand
+  uint32_t free_mask[kPassMax];  // tile bits that index superoperator j's groups
+  uint32_t stj[kPassMax][16];    // S(tile-local index of local index l) of superoperator j
+  uint8_t xcol[16];              // swizzle column of each tile bit (0 inside the window)
+  uint8_t vpos[16];              // tile bit b -> global bit vpos[b] (ascending)
+  uint8_t run_src[16];           // runs of fixed bits (up to 13 around 12 target bits)
+  uint8_t run_len[16];
+  uint8_t run_dst[16];
+};
+
 // Fusion: a block of consecutive operations on at most k qubits.
 struct FuseOpDev {
   int32_t j;          // qubits of the operation
@@ -117,6 +138,18 @@ int variant_for(int n, int k, tanq_prec p);
 int variant_find(int k, tanq_prec p, int tile_bits, int threads, int staging);
 void launch_apply_variant(void* rho, int n, tanq_prec p, int k, int index, const int* qubits, const void* packed,
                           hipStream_t s);
+
+// Passes (pass.hip): tile bits per precision; geometry of m superoperators (qubits: m pairs,
+// op_off: element offsets of their packed operands); launch on one state.
+int pass_tile_bits(tanq_prec p);
+// conflict_free (optional): access patterns (two per superoperator) whose LDS reads and writes
+// are free of bank conflicts under the chosen swizzle.
+PassGeom make_pass_geom(int n, int m, const int* qubits, const uint32_t* op_off, tanq_prec p,
+                        int* conflict_free = nullptr);
+void launch_pass(void* rho, tanq_prec p, const PassGeom& g, const void* frags, hipStream_t s);
+// Process-wide limit on superoperators per pass (1 = no passes).
+int pass_limit();
+void set_pass_limit(int m);
 
 void launch_init_zero(void* rho, int n, tanq_prec p, hipStream_t s);
 void launch_gather(const void* rho, tanq_prec p, const uint64_t* idx_dev, size_t count, void* out_dev,

@@ -1,0 +1,452 @@
+// Multi-superoperator passes (gfx950): several consecutive 2-qubit superoperators applied to
+// each tile of vec(rho) while it sits in LDS, so the state crosses HBM once per pass instead of
+// once per superoperator.
+//
+// A pass is a run of fused 2-qubit blocks whose qubits together number at most V/2 (the tile
+// holds the row and column bit of every one of them, plus the lowest other bits up to V).  For
+// each superoperator of the pass the tile splits into 2^(V-4) groups of 16 elements, indexed by
+// the tile bits that are not its targets; the multiplication of every group is exactly the one
+// the single-superoperator kernel performs (the same real-block MFMA sequence, Sec. 3.1-3.2's
+// batched GEMM), only the addresses differ.  Superoperators follow one another in circuit
+// order, separated by an LDS barrier, so the result is the same as applying them one by one.
+//
+// LDS swizzle.  One LDS layout serves every superoperator of the pass, so the swizzle is a
+// linear map over GF(2): element e lives at S(e) = e ^ X(e), where X XORs a W-bit value (W = 4
+// for FP64, 5 for FP32: the 256-byte bank window) for each set bit of e above the window.  X
+// depends only on bits above the window, so S permutes every window (the 16-byte load and store
+// phases stay conflict-free) and S is its own inverse.  The host picks X so that, for every
+// superoperator, the 16 groups an MFMA column block reads land on distinct banks (and, for FP32,
+// also the two rows each lane pair covers); by linearity S(tile index of a target part + group
+// part) = S(target part) ^ S(group part), so the target offsets are swizzled once on the host.
+#include <atomic>
+#include <cstring>
+
+#include "tile.hpp"
+
+namespace tanq {
+
+namespace {
+
+template <typename T>
+struct PassWin;
+template <>
+struct PassWin<double> { static constexpr int W = 4; };
+template <>
+struct PassWin<float> { static constexpr int W = 5; };
+
+template <typename T>
+__device__ inline uint32_t pass_swz(uint32_t e, const PassGeom& g) {
+  uint32_t x = e;
+#pragma unroll
+  for (int b = PassWin<T>::W; b < 16; ++b)
+    if ((e >> b) & 1u) x ^= g.xcol[b];
+  return x;
+}
+
+__device__ inline uint64_t pass_tile_base(const PassGeom& g, uint64_t tile) {
+  uint64_t b = 0;
+#pragma unroll
+  for (int r = 0; r < 16; ++r)  // constant indices keep the run table in scalar registers
+    if (r < g.nruns) b |= ((tile >> g.run_src[r]) & ((1ull << g.run_len[r]) - 1ull)) << g.run_dst[r];
+  return b;
+}
+
+}  // namespace
+
+// Persistent grid over full tiles (2^VMAX elements); the next tile is prefetched into registers
+// while the current one goes through the pass, as in the single-superoperator kernel.
+template <typename T, int VMAX, int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void apply_pass_kernel(T* __restrict__ rho, const T* __restrict__ frags,
+                                                        const PassGeom g) {
+  using M = Mfma<T>;
+  using acc_t = typename M::acc_t;
+  using c2 = typename M::c2;
+  constexpr int EPS = 16 / (2 * (int)sizeof(T));  // elements per 16-byte slot
+  constexpr int SLOTS = (1 << VMAX) / EPS;
+  constexpr int ITERS = SLOTS / NT;
+  static_assert(SLOTS % NT == 0, "whole slots per thread");
+  constexpr int NW = NT / 64;
+  constexpr int NB = (1 << (VMAX - 4)) / 16;  // 16-group column blocks per superoperator
+  constexpr int NBW = NB / NW;
+  static_assert(NB % NW == 0, "every wave gets the same number of column blocks");
+  constexpr int MT = 2, KS = 8;
+
+  constexpr int G = 1 << (VMAX - 4);  // groups of one superoperator in a tile
+  __shared__ u32x4 lds[SLOTS];
+  // swizzled tile index of group gi of superoperator j (the same for every tile)
+  __shared__ uint16_t gxt[kPassMax][G];
+  T* ldsT = reinterpret_cast<T*>(lds);
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int kk = lane >> 4;  // B row within a k-step
+  const int cc = kk & 1;     // re / im of that row
+  const int hb = kk >> 1;    // low complex bit of that row
+
+  // FP32 moves two elements per 16-byte slot; the swizzle keeps them in one slot (X does not
+  // depend on bit 0) but may swap their order, which the load and store phases undo
+  uint64_t off[ITERS];
+  uint32_t lslot[ITERS];
+  bool swap[ITERS];
+#pragma unroll
+  for (int it = 0; it < ITERS; ++it) {
+    const uint32_t j = (uint32_t)((it * NT + tid) * EPS);
+    uint64_t o = 0;
+    for (int b = 0; b < VMAX; ++b) o |= (uint64_t)((j >> b) & 1u) << g.vpos[b];
+    off[it] = o;
+    const uint32_t sj = pass_swz<T>(j, g);
+    lslot[it] = sj / EPS;
+    swap[it] = EPS == 2 && ((sj ^ j) & 1u);
+  }
+  auto order = [&](u32x4 v, int it) { return swap[it] ? u32x4{v[2], v[3], v[0], v[1]} : v; };
+
+  uint64_t tile = xcd_first_tile();
+  if (tile >= g.ntiles) return;  // uniform per workgroup
+  for (int idx = tid; idx < g.m * G; idx += NT) {
+    const int j = idx / G, gi = idx % G;
+    gxt[j][gi] = (uint16_t)pass_swz<T>(pdep32((uint32_t)gi, g.free_mask[j]), g);
+  }
+  uint64_t cur = pass_tile_base(g, tile);
+  u32x4 buf[ITERS];
+#pragma unroll
+  for (int it = 0; it < ITERS; ++it) buf[it] = *reinterpret_cast<const u32x4*>(rho + 2 * (cur + off[it]));
+#pragma unroll
+  for (int it = 0; it < ITERS; ++it) lds[lslot[it]] = order(buf[it], it);
+  lds_barrier();
+
+  for (;;) {
+    const uint64_t next = tile + gridDim.x;
+    const bool more = next < g.ntiles;
+    uint64_t nbase = 0;
+    if (more) {
+      nbase = pass_tile_base(g, next);
+#pragma unroll
+      for (int it = 0; it < ITERS; ++it) buf[it] = *reinterpret_cast<const u32x4*>(rho + 2 * (nbase + off[it]));
+    }
+
+    for (int j = 0; j < g.m; ++j) {
+      T afr[MT][KS];
+      const T* fr = frags + g.op_off[j];
+#pragma unroll
+      for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int s = 0; s < KS; ++s) afr[m][s] = fr[(m * KS + s) * 64 + lane];
+      const uint32_t* st = g.stj[j];
+      const uint32_t s1 = hb ? st[1] : 0u;
+#pragma unroll
+      for (int i = 0; i < NBW; ++i) {
+        const uint32_t gx = gxt[j][(wave + i * NW) * 16 + (lane & 15)];
+        acc_t acc[MT];
+#pragma unroll
+        for (int m = 0; m < MT; ++m) acc[m] = acc_t{0, 0, 0, 0};
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+          const uint32_t e = (st[2 * s] ^ s1) ^ gx;
+          const T b = ldsT[2 * e + cc];
+#pragma unroll
+          for (int m = 0; m < MT; ++m) acc[m] = M::mma(afr[m][s], b, acc[m]);
+        }
+        // a wave writes only the groups it read, so no barrier inside one superoperator
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+          if constexpr (M::kRowsStrided) {
+            // value r = real row kk + 4r of m-tile m: component cc of output a = 8m + 2r + hb
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const uint32_t e = (st[8 * m] ^ st[2 * r] ^ s1) ^ gx;
+              ldsT[2 * e + cc] = acc[m][r];
+            }
+          } else {
+            // values (0,1), (2,3) = (re, im) of outputs a = 8m + 2kk and a + 1
+            const uint32_t tq = ((kk & 1) ? st[2] : 0u) ^ ((kk & 2) ? st[4] : 0u);
+            const uint32_t e0 = (st[8 * m] ^ tq) ^ gx;
+            const uint32_t e1 = e0 ^ st[1];
+            *reinterpret_cast<c2*>(ldsT + 2 * e0) = c2{acc[m][0], acc[m][1]};
+            *reinterpret_cast<c2*>(ldsT + 2 * e1) = c2{acc[m][2], acc[m][3]};
+          }
+        }
+      }
+      lds_barrier();  // the next superoperator reads groups other waves wrote
+    }
+
+#pragma unroll
+    for (int it = 0; it < ITERS; ++it) *reinterpret_cast<u32x4*>(rho + 2 * (cur + off[it])) = order(lds[lslot[it]], it);
+    if (!more) break;
+    lds_barrier();  // every store-phase LDS read is done before the next tile lands
+#pragma unroll
+    for (int it = 0; it < ITERS; ++it) lds[lslot[it]] = order(buf[it], it);
+    lds_barrier();
+    tile = next;
+    cur = nbase;
+  }
+}
+
+// Tile shapes: 2^12 FP64 elements (64 KiB, six qubits) with 512 threads; 2^13 FP32 elements
+// (64 KiB, six qubits and one more bit) with 512 threads.
+template <typename T>
+struct PassShape;
+template <>
+struct PassShape<double> { static constexpr int V = 12, NT = 512; };
+template <>
+struct PassShape<float> { static constexpr int V = 13, NT = 512; };
+
+int pass_tile_bits(tanq_prec p) { return p == TANQ_F64 ? PassShape<double>::V : PassShape<float>::V; }
+
+static std::atomic<int> g_pass_limit{kPassMax};
+int pass_limit() { return g_pass_limit.load(); }
+void set_pass_limit(int m) {
+  if (m < 1 || m > kPassMax) fail(TANQ_E_ARG, "pass limit must be 1..8");
+  g_pass_limit.store(m);
+}
+
+// ------------------------------------------------------------------------------------
+// host: geometry and swizzle of one pass
+// ------------------------------------------------------------------------------------
+
+namespace {
+
+int gf2_rank(uint32_t* v, int cnt) {
+  int r = 0;
+  for (int bit = 31; bit >= 0 && r < cnt; --bit) {
+    int piv = -1;
+    for (int i = r; i < cnt; ++i)
+      if ((v[i] >> bit) & 1u) {
+        piv = i;
+        break;
+      }
+    if (piv < 0) continue;
+    std::swap(v[r], v[piv]);
+    for (int i = 0; i < cnt; ++i)
+      if (i != r && ((v[i] >> bit) & 1u)) v[i] ^= v[r];
+    ++r;
+  }
+  return r;
+}
+
+struct SwzProblem {
+  int W, V, m;
+  uint32_t fbits[kPassMax][4];  // lowest four free tile bits of each superoperator
+  uint32_t t1[kPassMax], t2[kPassMax];
+};
+
+uint32_t low_of(uint32_t x, const uint8_t* xcol, int W) {
+  uint32_t r = x & ((1u << W) - 1u);
+  for (int b = W; b < 16; ++b)
+    if ((x >> b) & 1u) r ^= xcol[b];
+  return r;
+}
+
+// Number of bank-conflict-free access patterns under xcol (2 per superoperator).
+int swz_score(const SwzProblem& P, const uint8_t* xcol) {
+  int score = 0;
+  for (int j = 0; j < P.m; ++j) {
+    uint32_t v[5];
+    if (P.W == 4) {
+      for (int q = 0; q < 4; ++q) v[q] = low_of(1u << P.fbits[j][q], xcol, 4);
+      score += 2 * (gf2_rank(v, 4) == 4);
+    } else {
+      for (int q = 0; q < 4; ++q) v[q] = low_of(1u << P.fbits[j][q], xcol, 5);
+      v[4] = low_of(P.t1[j], xcol, 5);
+      score += gf2_rank(v, 5) == 5;
+      for (int q = 0; q < 4; ++q) v[q] = low_of(1u << P.fbits[j][q], xcol, 5);
+      v[4] = low_of(P.t2[j], xcol, 5);
+      score += gf2_rank(v, 5) == 5;
+    }
+  }
+  return score;
+}
+
+// Upper bound of swz_score over all swizzles: a pattern's vectors from bits inside the window
+// are fixed unit vectors; those from bits above it can be any vectors, so a pattern can reach
+// full rank only if its fixed vectors are distinct.
+int swz_bound(const SwzProblem& P) {
+  auto ok = [&](const uint32_t* bits, int cnt) {
+    uint32_t fixed = 0;
+    int above = 0;
+    for (int q = 0; q < cnt; ++q) {
+      if (bits[q] < (uint32_t)P.W) {
+        if ((fixed >> bits[q]) & 1u) return false;  // a repeated unit vector
+        fixed |= 1u << bits[q];
+      } else {
+        ++above;
+      }
+    }
+    return above <= P.W - __builtin_popcount(fixed);
+  };
+  int b = 0;
+  for (int j = 0; j < P.m; ++j) {
+    uint32_t v[5];
+    for (int q = 0; q < 4; ++q) v[q] = P.fbits[j][q];
+    if (P.W == 4) {
+      b += 2 * ok(v, 4);
+    } else {
+      v[4] = (uint32_t)__builtin_ctz(P.t1[j]);
+      b += ok(v, 5);
+      v[4] = (uint32_t)__builtin_ctz(P.t2[j]);
+      b += ok(v, 5);
+    }
+  }
+  return b;
+}
+
+uint64_t splitmix(uint64_t& s) {
+  uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+}  // namespace
+
+PassGeom make_pass_geom(int n, int m, const int* qubits, const uint32_t* op_off, tanq_prec p, int* conflict_free) {
+  if (m < 1 || m > kPassMax) fail(TANQ_E_ARG, "pass length outside 1..kPassMax");
+  PassGeom g;
+  std::memset(&g, 0, sizeof(g));
+  const int nb = 2 * n;
+  const int V = pass_tile_bits(p);
+  if (nb < V) fail(TANQ_E_ARG, "state too small for a pass tile");
+  uint64_t vmask = 0;
+  for (int j = 0; j < m; ++j)
+    for (int t = 0; t < 2; ++t) {
+      const int q = qubits[2 * j + t];
+      if (q < 0 || q >= n) fail(TANQ_E_ARG, "pass qubit out of range");
+      vmask |= (1ull << q) | (1ull << (q + n));
+    }
+  if (__builtin_popcountll(vmask) > V) fail(TANQ_E_ARG, "pass qubits do not fit one tile");
+  for (int b = 0, need = V - __builtin_popcountll(vmask); b < nb && need > 0; ++b)
+    if (!((vmask >> b) & 1ull)) {
+      vmask |= 1ull << b;
+      --need;
+    }
+  int cnt = 0;
+  int local_of[64];
+  for (int b = 0; b < nb; ++b) {
+    local_of[b] = -1;
+    if ((vmask >> b) & 1ull) {
+      local_of[b] = cnt;
+      g.vpos[cnt++] = (uint8_t)b;
+    }
+  }
+  if (cnt != V) fail(TANQ_E_STATE, "pass tile bit count");
+  // FP32 moves two elements per 16-byte slot: global bit 0 must be tile bit 0
+  if (p != TANQ_F64 && g.vpos[0] != 0) fail(TANQ_E_STATE, "pass tile without global bit 0");
+  g.V = V;
+  g.m = m;
+
+  uint32_t tj[kPassMax][16];
+  SwzProblem P{};
+  P.W = (p == TANQ_F64) ? 4 : 5;
+  P.V = V;
+  P.m = m;
+  for (int j = 0; j < m; ++j) {
+    const int tgt[4] = {qubits[2 * j], qubits[2 * j + 1], qubits[2 * j] + n, qubits[2 * j + 1] + n};
+    uint32_t tmask = 0;
+    int tpos[4];
+    for (int t = 0; t < 4; ++t) {
+      tpos[t] = local_of[tgt[t]];
+      tmask |= 1u << tpos[t];
+    }
+    if (__builtin_popcount(tmask) != 4) fail(TANQ_E_ARG, "a pass superoperator repeats a qubit");
+    for (int l = 0; l < 16; ++l) {
+      uint32_t r = 0;
+      for (int t = 0; t < 4; ++t)
+        if ((l >> t) & 1) r |= 1u << tpos[t];
+      tj[j][l] = r;
+    }
+    g.free_mask[j] = ((1u << V) - 1u) & ~tmask;
+    g.op_off[j] = op_off[j];
+    int q = 0;
+    for (int b = 0; b < V && q < 4; ++b)
+      if ((g.free_mask[j] >> b) & 1u) P.fbits[j][q++] = (uint32_t)b;
+    P.t1[j] = tj[j][1];
+    P.t2[j] = tj[j][2];
+  }
+
+  // swizzle: the identity first, then seeded random candidates, keeping the best (reaching the
+  // bound ends the search)
+  uint8_t best[16] = {0};
+  int best_score = swz_score(P, best);
+  const int perfect = swz_bound(P);
+  uint64_t seed = 0x7A3Cull ^ ((uint64_t)n << 32) ^ (uint64_t)m;
+  const uint32_t wmask = (1u << P.W) - 1u;
+  for (int trial = 0; trial < 4000 && best_score < perfect; ++trial) {
+    uint8_t cand[16] = {0};
+    const uint64_t r0 = splitmix(seed), r1 = splitmix(seed);
+    for (int b = P.W; b < V; ++b) {
+      const uint64_t r = (b < 8 + P.W) ? (r0 >> (8 * (b - P.W))) : (r1 >> (8 * (b - P.W - 8)));
+      cand[b] = (uint8_t)((uint32_t)r & wmask);
+    }
+    const int sc = swz_score(P, cand);
+    if (sc > best_score) {
+      best_score = sc;
+      std::memcpy(best, cand, sizeof(best));
+    }
+  }
+  std::memcpy(g.xcol, best, sizeof(best));
+  if (conflict_free) *conflict_free = best_score;
+  auto S = [&](uint32_t e) {
+    uint32_t x = e;
+    for (int b = P.W; b < 16; ++b)
+      if ((e >> b) & 1u) x ^= g.xcol[b];
+    return x;
+  };
+  for (int j = 0; j < m; ++j)
+    for (int l = 0; l < 16; ++l) g.stj[j][l] = S(tj[j][l]);
+  // the swizzle is an involution of [0, 2^V) that keeps FP32 slot pairs in one slot
+  for (uint32_t e = 0; e < (1u << V); ++e) {
+    const uint32_t s = S(e);
+    if (s >= (1u << V) || S(s) != e || (S(e ^ 1u) != (s ^ 1u)))
+      fail(TANQ_E_STATE, "pass swizzle is not an involution");
+  }
+
+  // runs of fixed bits
+  int src = 0, nr = 0;
+  for (int b = 0; b < nb;) {
+    if ((vmask >> b) & 1ull) {
+      ++b;
+      continue;
+    }
+    int e = b;
+    while (e < nb && !((vmask >> e) & 1ull)) ++e;
+    if (nr >= 16) fail(TANQ_E_STATE, "too many runs of fixed bits");
+    g.run_src[nr] = (uint8_t)src;
+    g.run_len[nr] = (uint8_t)(e - b);
+    g.run_dst[nr] = (uint8_t)b;
+    src += e - b;
+    ++nr;
+    b = e;
+  }
+  g.nruns = nr;
+  g.ntiles = 1ull << (nb - V);
+  return g;
+}
+
+template <typename T>
+static void launch_pass_typed(void* rho, const PassGeom& g, const void* frags, hipStream_t s) {
+  constexpr int V = PassShape<T>::V, NT = PassShape<T>::NT;
+  if (g.V != V) fail(TANQ_E_STATE, "pass geometry built for another tile size");
+  auto kern = apply_pass_kernel<T, V, NT>;
+  static thread_local int cap_dev = -1;
+  static thread_local uint64_t cap = 0;
+  int dev = 0;
+  TANQ_HIP(hipGetDevice(&dev));
+  if (cap_dev != dev) {
+    int per_cu = 0;
+    TANQ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, NT, 0));
+    cap = (uint64_t)device_cu_count() * (uint64_t)(per_cu < 1 ? 1 : per_cu);
+    cap_dev = dev;
+  }
+  const uint64_t grid = g.ntiles < cap ? g.ntiles : cap;
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(NT), 0, s, (T*)rho, (const T*)frags, g);
+  TANQ_HIP(hipGetLastError());
+}
+
+void launch_pass(void* rho, tanq_prec p, const PassGeom& g, const void* frags, hipStream_t s) {
+  if (p == TANQ_F64)
+    launch_pass_typed<double>(rho, g, frags, s);
+  else
+    launch_pass_typed<float>(rho, g, frags, s);
+}
+
+}  // namespace tanq

@@ -42,6 +42,7 @@ EXPORTED = [
     "tanq_apply_superop", "tanq_apply_fused", "tanq_apply_fused_range",
     "tanq_variant_count", "tanq_variant_get", "tanq_variant_select", "tanq_variant_selected", "tanq_autotune",
     "tanq_variant_for", "tanq_tuning_export", "tanq_tuning_import", "tanq_autotune_dense",
+    "tanq_set_pass_limit", "tanq_get_pass_limit", "tanq_pass_layout_info", "tanq_fused_passes",
     "tanq_probs", "tanq_probs_readout", "tanq_sample", "tanq_dm_set_basis", "tanq_reduced_dm",
     "tanq_process_chi_1q",
     "tanq_expect_pauli", "tanq_expect_pauli_c", "tanq_expect_pauli_batch",
@@ -135,6 +136,10 @@ _SIGS = {
     "tanq_dm_set_basis": ([_vp, ctypes.c_uint64, ctypes.c_uint64], ctypes.c_int),
     "tanq_variant_for": ([ctypes.c_int, ctypes.c_int, ctypes.c_int, _ip], ctypes.c_int),
     "tanq_autotune_dense": ([_vp, ctypes.c_int, _dp], ctypes.c_int),
+    "tanq_set_pass_limit": ([ctypes.c_int], ctypes.c_int),
+    "tanq_get_pass_limit": ([_ip], ctypes.c_int),
+    "tanq_pass_layout_info": ([ctypes.c_int, ctypes.c_int, _ip, ctypes.c_int, _ip], ctypes.c_int),
+    "tanq_fused_passes": ([_vp, _ip, _ip], ctypes.c_int),
     "tanq_tuning_export": ([ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "tanq_tuning_import": ([ctypes.c_char_p], ctypes.c_int),
     "tanq_reduced_dm": ([_vp, ctypes.c_int, _ip, _dp], ctypes.c_int),
@@ -396,6 +401,31 @@ def tanq_probs_readout(h: int, n: int, p01, p10) -> np.ndarray:
 def tanq_variant_for(n: int, k: int, prec) -> int:
     v = ctypes.c_int()
     _check(load().tanq_variant_for(n, k, _prec(prec), ctypes.byref(v)))
+    return v.value
+
+
+def tanq_set_pass_limit(max_superops: int):
+    _check(load().tanq_set_pass_limit(int(max_superops)))
+
+
+def tanq_get_pass_limit() -> int:
+    v = ctypes.c_int()
+    _check(load().tanq_get_pass_limit(ctypes.byref(v)))
+    return v.value
+
+
+def tanq_fused_passes(h: int):
+    """(passes, blocks applied inside passes) of a fused list under the current pass limit."""
+    a, b = ctypes.c_int(), ctypes.c_int()
+    _check(load().tanq_fused_passes(h, ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
+def tanq_pass_layout_info(n: int, pairs: Sequence[Sequence[int]], prec) -> int:
+    """Conflict-free LDS access patterns (of 2 per superoperator) of one pass layout."""
+    flat = [int(q) for pr in pairs for q in pr]
+    v = ctypes.c_int()
+    _check(load().tanq_pass_layout_info(n, len(pairs), _ints(flat), _prec(prec), ctypes.byref(v)))
     return v.value
 
 
@@ -682,6 +712,10 @@ class Fused:
 
     def get(self, idx: int):
         return tanq_fused_get(self.h, idx)
+
+    def passes(self):
+        """(passes, blocks inside passes) that apply_fused uses under the current pass limit."""
+        return tanq_fused_passes(self.h)
 
     def get_k(self, idx: int) -> int:
         if getattr(self, "_ks", None) is None:

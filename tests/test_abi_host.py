@@ -149,3 +149,44 @@ def test_empty_circuit_plans_no_blocks(lib):
         blocks, nb = c.plan(mode)
         assert nb == 0 and blocks == []
     c.free()
+
+
+def test_pass_limit_roundtrip(lib):
+    old = T.tanq_get_pass_limit()
+    try:
+        for m in (1, 2, 8):
+            T.tanq_set_pass_limit(m)
+            assert T.tanq_get_pass_limit() == m
+        for bad in (0, 9, -1):
+            with pytest.raises(T.TanqError):
+                T.tanq_set_pass_limit(bad)
+        assert T.tanq_get_pass_limit() == 8
+    finally:
+        T.tanq_set_pass_limit(old)
+
+
+def test_pass_layouts_are_bank_conflict_free(lib):
+    """The swizzle search finds a conflict-free LDS layout for seeded random passes of up to
+    six qubits (FP32 always; FP64 all but a few placements whose lowest free bits collide)."""
+    rng = np.random.default_rng(17)
+    perfect = {"f64": 0, "f32": 0}
+    trials = 150
+    for prec in perfect:
+        for _ in range(trials):
+            n = int(rng.integers(7, 17))
+            qs = [int(x) for x in rng.choice(n, 6, replace=False)]
+            m = int(rng.integers(2, 9))
+            pairs = [tuple(int(x) for x in rng.choice(qs, 2, replace=False)) for _ in range(m)]
+            sc = T.tanq_pass_layout_info(n, pairs, prec)
+            assert 0 <= sc <= 2 * m
+            perfect[prec] += sc == 2 * m
+    assert perfect["f32"] == trials
+    assert perfect["f64"] >= trials - 5
+
+
+def test_pass_layout_rejects_invalid(lib):
+    for pairs in ([(0, 0)], [(0, 1), (2, 3), (4, 5), (6, 7)], [(0, 16)], [(0, 1)] * 9):
+        with pytest.raises(T.TanqError):
+            T.tanq_pass_layout_info(16, pairs, "f64")
+    with pytest.raises(T.TanqError):  # 2n = 10 < 12 tile bits
+        T.tanq_pass_layout_info(5, [(0, 1), (2, 3)], "f64")

@@ -1,0 +1,109 @@
+"""Multi-superoperator passes: runs of 2-qubit blocks applied in one pass over vec(rho).
+
+Each pass performs, per superoperator, the same per-group MFMA sequence as a single apply, so
+the state after tanq_apply_fused with passes must equal, bit for bit, the state with passes
+switched off (limit 1); FP64 must also match the CPU oracle within 1e-10.  Sizes: the smallest
+states that hold a pass tile (n = 6 in FP64, n = 7 in FP32), a mid size, and a 12-qubit state
+compared on every element.  Circuits: the random U3/CX circuit (random pairs, so passes mix
+low and high qubits) and the nearest-neighbour brickwork (passes on neighbouring qubits, low
+qubits inside the bank window)."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2404_13184_amd import tanq as T
+from paper_2404_13184_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def run_fused(n, ops, prec, limit, rho_in=None):
+    old = T.tanq_get_pass_limit()
+    T.tanq_set_pass_limit(limit)
+    try:
+        c = T.Circuit(n, ops)
+        f = c.fuse(2, prec)
+        passes = f.passes()
+        d = T.DM(n, prec)
+        if rho_in is not None:
+            d.write(rho_in)
+        d.apply_fused(f)
+        out = d.read()
+        d.free()
+        f.free()
+        c.free()
+        return out, passes
+    finally:
+        T.tanq_set_pass_limit(old)
+
+
+def circuits(n):
+    return [("u3cx", W.random_u3_cx(n, 6, 11 + n, 1e-3, 1e-2, gamma=5e-4)),
+            ("brick", W.brickwork_cz(n, 6, 7 + n, 1e-3, 1e-2, 1e-3))]
+
+
+@pytest.mark.parametrize("prec,n", [("f64", 6), ("f64", 8), ("f32", 7), ("f32", 8)])
+def test_passes_bitwise_equal_to_single_applies(prec, n):
+    for name, ops in circuits(n):
+        say("passes %s n=%d %s" % (prec, n, name))
+        want, p0 = run_fused(n, ops, prec, 1)
+        got, p1 = run_fused(n, ops, prec, 8)
+        assert p0 == (0, 0)
+        assert p1[0] > 0 and p1[1] >= 2 * p1[0]  # passes were used
+        assert np.array_equal(got.view(np.uint8), want.view(np.uint8))
+
+
+@pytest.mark.parametrize("limit", [2, 3, 5])
+def test_pass_limits(limit):
+    n = 8
+    ops = W.random_u3_cx(n, 5, 3, 1e-3, 1e-2)
+    say("pass limit %d" % limit)
+    want, _ = run_fused(n, ops, "f64", 1)
+    got, (np_, nin) = run_fused(n, ops, "f64", limit)
+    assert np_ > 0 and nin <= limit * np_
+    assert np.array_equal(got.view(np.uint8), want.view(np.uint8))
+
+
+def test_passes_match_oracle_f64(oracle_mod):
+    n = 7
+    for name, ops in circuits(n):
+        say("passes vs oracle n=%d %s" % (n, name))
+        got, (np_, _) = run_fused(n, ops, "f64", 8)
+        assert np_ > 0
+        want = oracle_mod.matrix_to_vec(oracle_mod.run(n, ops))
+        assert np.abs(got - want).max() <= 1e-10
+
+
+def test_passes_on_a_dense_input_f32(oracle_mod):
+    """FP32 against the FP64 oracle from a dense random state (every element nonzero)."""
+    n = 7
+    rng = np.random.default_rng(5)
+    A = rng.standard_normal((1 << n, 1 << n)) + 1j * rng.standard_normal((1 << n, 1 << n))
+    rho = A @ A.conj().T
+    rho /= np.trace(rho)
+    vec = oracle_mod.matrix_to_vec(rho)
+    ops = W.random_u3_cx(n, 4, 21, 1e-3, 1e-2)
+    say("passes f32 dense n=%d" % n)
+    got, (np_, _) = run_fused(n, ops, "f32", 8, rho_in=vec.astype(np.complex64))
+    assert np_ > 0
+    want = oracle_mod.matrix_to_vec(oracle_mod.run(n, ops, rho))
+    g = oracle_mod.vec_to_matrix(got.astype(np.complex128), n)
+    w = oracle_mod.vec_to_matrix(want, n)
+    assert oracle_mod.trace_distance(g, w) <= 1e-4
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_passes_bitwise_12_qubits(prec):
+    n = 12
+    ops = W.random_u3_cx(n, 3, 12, 1e-3, 1e-2, gamma=5e-4)
+    say("passes %s n=%d full compare" % (prec, n))
+    want, _ = run_fused(n, ops, prec, 1)
+    got, (np_, _) = run_fused(n, ops, prec, 8)
+    assert np_ > 0
+    assert np.array_equal(got.view(np.uint8), want.view(np.uint8))
