@@ -130,6 +130,25 @@ def run_precision(T, torch, n, ops, prec, width, steps, warmup):
         f.free()
         return info, p, tr
 
+    # multi-superoperator passes: the circuit fused at width 2, whose runs of 2-qubit blocks are
+    # applied several per pass over the state; one whole apply_fused, timed end to end
+    d.reset()
+    f2 = circ.fuse(2, prec, stream)
+    npass, nin = f2.passes()
+    d.apply_fused(f2, 0, min(f2.count, 8))  # loads the kernels
+    d.reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    d.apply_fused(f2)
+    torch.cuda.synchronize()
+    T.tanq_sync(d.h)
+    dt = time.perf_counter() - t0
+    passes = {"fusion_width": 2, "fused_applies": f2.count, "passes": npass, "blocks_in_passes": nin,
+              "launches": npass + f2.count - nin, "s": round(dt, 3),
+              "applies_per_s": round(f2.count / dt, 3), "gates_per_s": round(len(ops) / dt, 1)}
+    f2.free()
+    log("%s width 2 with passes: %s" % (prec, passes))
+
     for w in range(warmup):
         one_step()
         log("%s warmup step %d done" % (prec, w + 1))
@@ -147,7 +166,7 @@ def run_precision(T, torch, n, ops, prec, width, steps, warmup):
     circ.free()
     applies = info["count"] * steps
     return {"wall_s": wall, "applies": applies, "info": info, "per_k": per_k, "trace": tr, "probs": p,
-            "tuned_ms": tuned_ms[1:], "variants": variants}, d
+            "tuned_ms": tuned_ms[1:], "variants": variants, "passes": passes}, d
 
 
 def roofline(prec, k, n, secs):
@@ -381,7 +400,7 @@ def main():
                      "avg_launch_ms_by_k": {str(k): round(sum(v) / len(v) * 1e3, 3) for k, v in rr["per_k"].items()},
                      "roofline": dominant(rr, prec), "trace": rr["trace"],
                      "autotuned_ms_per_apply_by_k": [round(x, 3) for x in rr["tuned_ms"]],
-                     "variants": rr["variants"]}
+                     "variants": rr["variants"], "width2_with_passes": rr["passes"]}
     if accuracy is not None:
         out["f32_vs_f64"] = accuracy
     if a.serve_requests > 0:
