@@ -203,6 +203,7 @@ template <typename BlockAt>
 int pass_run(BlockAt at, int i, int end, int n, tanq_prec p, int lim) {
   const int V = pass_tile_bits(p);
   const int min_run = p == TANQ_F64 ? 3 : 4;  // 8 x 16 B or 16 x 8 B
+  lim = std::min(lim, pass_max(p));
   if (lim < 2 || 2 * n < V) return 1;
   const int* q = nullptr;
   if (at(i, &q) != 2) return 1;

@@ -142,6 +142,8 @@ void launch_apply_variant(void* rho, int n, tanq_prec p, int k, int index, const
 // Passes (pass.hip): tile bits per precision; geometry of m superoperators (qubits: m pairs,
 // op_off: element offsets of their packed operands); launch on one state.
 int pass_tile_bits(tanq_prec p);
+// Most superoperators one pass of precision p holds (at most kPassMax).
+int pass_max(tanq_prec p);
 // conflict_free (optional): access patterns (two per superoperator) whose LDS reads and writes
 // are free of bank conflicts under the chosen swizzle.
 PassGeom make_pass_geom(int n, int m, const int* qubits, const uint32_t* op_off, tanq_prec p,

@@ -182,6 +182,148 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void ap
   }
 }
 
+// FP64 passes with specialised waves, one workgroup per CU.  NPW producer waves stream the next
+// tile into one of two LDS buffers with direct global-to-LDS loads while NCW consumer waves
+// multiply the current tile in the other and store it.  The roles run separate loops, so the
+// consumers' LDS reads are never preceded by a global-to-LDS load in their own instruction
+// stream (the compiler would otherwise wait for every such load before the first read).  Both
+// loops execute the same barriers, in the same order, per tile (all counts are uniform):
+//   B0 (tile ready) -- m barriers, one after each superoperator -- B_free (buffer read out);
+// the producer issues the next tile's loads right after B0 and waits for them before the next
+// B0, so they stream during the whole multiplication and store of the current tile.
+constexpr int kPassWsMax = 3;  // superoperators per FP64 pass (their operands live in LDS)
+
+// Global offset of the tile element held by LDS slot p (S is an involution: slot p holds S(p)).
+template <int VMAX>
+__device__ inline uint64_t pass_slot_off(uint32_t p, const PassGeom& g) {
+  const uint32_t e = pass_swz<double>(p, g);
+  uint64_t o = 0;
+  for (int b = 0; b < VMAX; ++b) o |= (uint64_t)((e >> b) & 1u) << g.vpos[b];
+  return o;
+}
+
+// One superoperator of an FP64 pass on the tile in ldsT, by consumer wave cw of NCW.
+template <int VMAX, int NCW>
+__device__ inline void pass_superop_f64(double* ldsT, const double (*opl)[1024], const uint16_t (*gxt)[1 << (VMAX - 4)],
+                                        const PassGeom& g, int j, int cw, int lane) {
+  using M = Mfma<double>;
+  using acc_t = typename M::acc_t;
+  constexpr int NB = (1 << (VMAX - 4)) / 16;
+  constexpr int NBW = NB / NCW;
+  static_assert(NB % NCW == 0, "every consumer wave gets the same number of column blocks");
+  constexpr int MT = 2, KS = 8;
+  const int kk = lane >> 4, cc = kk & 1, hb = kk >> 1;
+  double afr[MT][KS];
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int s = 0; s < KS; ++s) afr[m][s] = opl[j][(m * KS + s) * 64 + lane];
+  const uint32_t* st = g.stj[j];
+  const uint32_t s1 = hb ? st[1] : 0u;
+#pragma unroll
+  for (int i = 0; i < NBW; ++i) {
+    const uint32_t gx = gxt[j][(cw + i * NCW) * 16 + (lane & 15)];
+    acc_t acc[MT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) acc[m] = acc_t{0, 0, 0, 0};
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      const double bv = ldsT[2 * ((st[2 * s] ^ s1) ^ gx) + cc];
+#pragma unroll
+      for (int m = 0; m < MT; ++m) acc[m] = M::mma(afr[m][s], bv, acc[m]);
+    }
+    // a wave writes only the groups it read, so no barrier inside one superoperator
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) ldsT[2 * ((st[8 * m] ^ st[2 * r] ^ s1) ^ gx) + cc] = acc[m][r];
+  }
+}
+
+// Producer: stream one tile into buf with direct global-to-LDS loads (lane data lands at the
+// wave's base + 16 * lane, so slot it * PT + tid receives the element at offset off[it]).
+template <int PITERS, int PT>
+__device__ inline void pass_dma_tile(const double* rho, uint64_t base, const uint64_t (&off)[PITERS], u32x4* buf,
+                                     int wave) {
+#pragma unroll
+  for (int it = 0; it < PITERS; ++it)
+    __builtin_amdgcn_global_load_lds(rho + 2 * (base + off[it]), buf + it * PT + wave * 64, 16, 0, 0);
+}
+
+template <int VMAX, int NT, int NPW>
+__global__ __launch_bounds__(NT) void apply_pass_ws_kernel(double* __restrict__ rho, const double* __restrict__ frags,
+                                                           const PassGeom g) {
+  constexpr int NCW = NT / 64 - NPW;
+  constexpr int SLOTS = 1 << VMAX;             // one FP64 complex element per 16-byte slot
+  constexpr int PT = NPW * 64, CT = NCW * 64;  // producer and consumer threads
+  constexpr int PITERS = SLOTS / PT;           // loads per producer lane per tile
+  constexpr int CITERS = SLOTS / CT;           // stores per consumer thread per tile
+  static_assert(SLOTS % PT == 0 && SLOTS % CT == 0, "whole slots per thread");
+  constexpr int G = 1 << (VMAX - 4);
+
+  __shared__ u32x4 ldsA[SLOTS];
+  __shared__ u32x4 ldsB[SLOTS];
+  __shared__ double opl[kPassWsMax][1024];
+  __shared__ uint16_t gxt[kPassWsMax][G];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+
+  uint64_t tile = xcd_first_tile();
+  if (tile >= g.ntiles) return;  // uniform per workgroup
+  for (int idx = tid; idx < g.m * 1024; idx += NT) opl[idx >> 10][idx & 1023] = frags[g.op_off[idx >> 10] + (idx & 1023)];
+  for (int idx = tid; idx < g.m * G; idx += NT) {
+    const int j = idx / G, gi = idx % G;
+    gxt[j][gi] = (uint16_t)pass_swz<double>(pdep32((uint32_t)gi, g.free_mask[j]), g);
+  }
+  lds_barrier();  // operands and table in place before the roles split
+
+  if (wave < NPW) {
+    // ---------------- producer ----------------
+    uint64_t off[PITERS];
+#pragma unroll
+    for (int it = 0; it < PITERS; ++it) off[it] = pass_slot_off<VMAX>((uint32_t)(it * PT + tid), g);
+    pass_dma_tile<PITERS, PT>(rho, pass_tile_base(g, tile), off, ldsA, wave);
+    vm_wait<0>();
+    raw_barrier();  // B0: first tile ready
+    for (int t = 0;; ++t) {
+      const uint64_t next = tile + gridDim.x;
+      const bool more = next < g.ntiles;
+      if (more) pass_dma_tile<PITERS, PT>(rho, pass_tile_base(g, next), off, (t & 1) ? ldsA : ldsB, wave);
+      for (int j = 0; j <= g.m; ++j) raw_barrier();  // the m superoperators, then B_free
+      if (!more) break;
+      vm_wait<0>();
+      raw_barrier();  // B0: next tile ready
+      tile = next;
+    }
+  } else {
+    // ---------------- consumers ----------------
+    const int cw = wave - NPW;  // consumer wave 0..NCW-1
+    const int ct = tid - PT;    // consumer thread 0..CT-1
+    uint64_t off[CITERS];
+#pragma unroll
+    for (int it = 0; it < CITERS; ++it) off[it] = pass_slot_off<VMAX>((uint32_t)(it * CT + ct), g);
+    raw_barrier();  // B0: first tile ready
+    for (int t = 0;; ++t) {
+      const uint64_t cur = pass_tile_base(g, tile);
+      const uint64_t next = tile + gridDim.x;
+      const bool more = next < g.ntiles;
+      u32x4* buf = (t & 1) ? ldsB : ldsA;
+      for (int j = 0; j < g.m; ++j) {
+        pass_superop_f64<VMAX, NCW>(reinterpret_cast<double*>(buf), opl, gxt, g, j, cw, lane);
+        raw_barrier();  // the next superoperator (or the store) reads what other waves wrote
+      }
+#pragma unroll
+      for (int it = 0; it < CITERS; ++it) *reinterpret_cast<u32x4*>(rho + 2 * (cur + off[it])) = buf[it * CT + ct];
+      raw_barrier();  // B_free: this buffer is read out
+      if (!more) break;
+      raw_barrier();  // B0: next tile ready
+      tile = next;
+    }
+  }
+}
+
 // Tile shapes: 2^12 FP64 elements (64 KiB, six qubits) with 512 threads; 2^13 FP32 elements
 // (64 KiB, six qubits and one more bit) with 512 threads.
 template <typename T>
@@ -192,6 +334,7 @@ template <>
 struct PassShape<float> { static constexpr int V = 13, NT = 512; };
 
 int pass_tile_bits(tanq_prec p) { return p == TANQ_F64 ? PassShape<double>::V : PassShape<float>::V; }
+int pass_max(tanq_prec p) { return p == TANQ_F64 ? kPassWsMax : kPassMax; }
 
 static std::atomic<int> g_pass_limit{kPassMax};
 int pass_limit() { return g_pass_limit.load(); }
@@ -442,9 +585,31 @@ static void launch_pass_typed(void* rho, const PassGeom& g, const void* frags, h
   TANQ_HIP(hipGetLastError());
 }
 
+// FP64 wave-specialised shape: 640 threads, 2 producer and 8 consumer waves.
+
+template <int V, int NT, int NPW>
+static void launch_pass_ws(void* rho, const PassGeom& g, const void* frags, hipStream_t s) {
+  if (g.V != V) fail(TANQ_E_STATE, "pass geometry built for another tile size");
+  if (g.m < 1 || g.m > kPassWsMax) fail(TANQ_E_STATE, "FP64 pass longer than its operand buffers");
+  auto kern = apply_pass_ws_kernel<V, NT, NPW>;
+  static thread_local int cap_dev = -1;
+  static thread_local uint64_t cap = 0;
+  int dev = 0;
+  TANQ_HIP(hipGetDevice(&dev));
+  if (cap_dev != dev) {
+    int per_cu = 0;
+    TANQ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, NT, 0));
+    cap = (uint64_t)device_cu_count() * (uint64_t)(per_cu < 1 ? 1 : per_cu);
+    cap_dev = dev;
+  }
+  const uint64_t grid = g.ntiles < cap ? g.ntiles : cap;
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(NT), 0, s, (double*)rho, (const double*)frags, g);
+  TANQ_HIP(hipGetLastError());
+}
+
 void launch_pass(void* rho, tanq_prec p, const PassGeom& g, const void* frags, hipStream_t s) {
   if (p == TANQ_F64)
-    launch_pass_typed<double>(rho, g, frags, s);
+    launch_pass_ws<PassShape<double>::V, 640, 2>(rho, g, frags, s);
   else
     launch_pass_typed<float>(rho, g, frags, s);
 }
