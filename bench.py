@@ -28,7 +28,9 @@ FP32_PEAK_TFLOPS = 157.3
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "apply_kernel_traffic_16q.txt")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2404_13184_amd", "csrc", f) for f in ("apply.hip", "tile.hpp")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2404_13184_amd", "csrc", f) for f in ("apply.hip", "tile.hpp", "pass.hip")]
+# multi-superoperator pass kernels, by precision
+PASS_KERNELS = {"f64": "apply_pass_ws_kernel<12, 640, 2>", "f32": "apply_pass_kernel<float, 13, 512>"}
 
 
 def kernel_source_hash() -> str:
@@ -118,36 +120,43 @@ def run_precision(T, torch, n, ops, prec, width, steps, warmup):
         if events is None:
             d.apply_fused(f)
         else:
-            for i in range(f.count):
+            # the launches apply_fused makes (single applies and multi-superoperator passes),
+            # each bracketed by events on the library's stream
+            pos = 0
+            for r in f.launches():
                 ev0 = torch.cuda.Event(enable_timing=True)
                 ev1 = torch.cuda.Event(enable_timing=True)
                 ev0.record(stream)
-                d.apply_fused(f, i, i + 1)
+                d.apply_fused(f, pos, pos + r)
                 ev1.record(stream)
-                events.append((f.get_k(i), ev0, ev1))
+                events.append((f.get_k(pos) if r == 1 else "pass", r, ev0, ev1))
+                pos += r
         p, tr = d.probs(renormalize=True)
         info = f.info
         f.free()
         return info, p, tr
 
-    # multi-superoperator passes: the circuit fused at width 2, whose runs of 2-qubit blocks are
-    # applied several per pass over the state; one whole apply_fused, timed end to end
+    # the other fusion width, for context: one whole apply_fused timed end to end
+    f0 = circ.fuse(width, prec, stream)
+    chosen = f0.info["max_width"]
+    f0.free()
+    alt_w = 3 if chosen == 2 else 2
     d.reset()
-    f2 = circ.fuse(2, prec, stream)
-    npass, nin = f2.passes()
-    d.apply_fused(f2, 0, min(f2.count, 8))  # loads the kernels
+    fa = circ.fuse(alt_w, prec, stream)
+    npass, nin = fa.passes()
+    d.apply_fused(fa, 0, min(fa.count, 8))  # loads the kernels
     d.reset()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    d.apply_fused(f2)
+    d.apply_fused(fa)
     torch.cuda.synchronize()
     T.tanq_sync(d.h)
     dt = time.perf_counter() - t0
-    passes = {"fusion_width": 2, "fused_applies": f2.count, "passes": npass, "blocks_in_passes": nin,
-              "launches": npass + f2.count - nin, "s": round(dt, 3),
-              "applies_per_s": round(f2.count / dt, 3), "gates_per_s": round(len(ops) / dt, 1)}
-    f2.free()
-    log("%s width 2 with passes: %s" % (prec, passes))
+    alternative = {"fusion_width": alt_w, "fused_applies": fa.count, "passes": npass, "blocks_in_passes": nin,
+                   "s": round(dt, 3), "applies_per_s": round(fa.count / dt, 3),
+                   "gates_per_s": round(len(ops) / dt, 1)}
+    fa.free()
+    log("%s fusion width %d (not chosen): %s" % (prec, alt_w, alternative))
 
     for w in range(warmup):
         one_step()
@@ -160,13 +169,16 @@ def run_precision(T, torch, n, ops, prec, width, steps, warmup):
         log("%s step %d done (%.1fs)" % (prec, st + 1, time.perf_counter() - t0))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    per_k = {}
-    for k, e0, e1 in events:
+    per_k, pass_sizes = {}, []
+    for k, r, e0, e1 in events:
         per_k.setdefault(k, []).append(e0.elapsed_time(e1) * 1e-3)
+        if r >= 2:
+            pass_sizes.append(r)
     circ.free()
     applies = info["count"] * steps
     return {"wall_s": wall, "applies": applies, "info": info, "per_k": per_k, "trace": tr, "probs": p,
-            "tuned_ms": tuned_ms[1:], "variants": variants, "passes": passes}, d
+            "tuned_ms": tuned_ms[1:], "variants": variants, "alternative": alternative,
+            "pass_sizes": pass_sizes, "launches": len(events) // max(steps, 1)}, d
 
 
 def roofline(prec, k, n, secs):
@@ -189,6 +201,21 @@ def roofline(prec, k, n, secs):
             "avg_launch_ms": round(secs * 1e3, 3), "algorithmic_flops": flops,
             "mfma_flops_executed": executed, "mfma_frac_executed": round(executed / secs / 1e12 / peak_f, 4),
             "hbm_GBs": round(nbytes / secs / 1e9, 1)}
+
+
+def roofline_pass(prec, n, secs, m_avg):
+    """A pass reads and writes the state once for m_avg 2-qubit superoperators: HBM-bound per
+    launch (the MFMA work of its superoperators is reported beside it)."""
+    es = 16 if prec == "f64" else 8
+    nbytes = 2.0 * (4 ** n) * es
+    flops = m_avg * 8.0 * 16 * (4 ** n)
+    peak_f = FP64_PEAK_TFLOPS if prec == "f64" else FP32_PEAK_TFLOPS
+    ach = nbytes / secs / 1e9
+    return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel_k": "pass",
+            "superops_per_launch": round(m_avg, 3), "avg_launch_ms": round(secs * 1e3, 3),
+            "algorithmic_bytes": nbytes, "algorithmic_flops": flops,
+            "mfma_frac": round(flops / secs / 1e12 / peak_f, 4)}
 
 
 def cpu_baseline(W, n_full, layers_full, cpu_n, budget_s):
@@ -360,6 +387,14 @@ def main():
     def dominant(rr, prec):
         k = max(rr["per_k"], key=lambda kk: sum(rr["per_k"][kk]))
         secs = sum(rr["per_k"][k]) / len(rr["per_k"][k])
+        if k == "pass":
+            rl = roofline_pass(prec, n, secs, sum(rr["pass_sizes"]) / len(rr["pass_sizes"]))
+            name = PASS_KERNELS[prec]
+            rl["kernel"] = name
+            rl["traffic"] = measured_traffic(name)
+            if rl["traffic"] is not None:
+                rl["traffic_unit"] = "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
+            return rl
         rl = roofline(prec, k, n, secs)
         if k in rr["variants"]:
             name = kernel_name(prec, k, rr["variants"][k])
@@ -397,10 +432,12 @@ def main():
                      "ms_per_step": round(rr["wall_s"] / a.steps * 1e3, 2),
                      "fused_applies": rr["info"]["count"], "fusion_width": rr["info"]["max_width"],
                      "count_by_k": rr["info"]["count_k"][1:],
-                     "avg_launch_ms_by_k": {str(k): round(sum(v) / len(v) * 1e3, 3) for k, v in rr["per_k"].items()},
+                     "avg_launch_ms_by_kind": {str(k): round(sum(v) / len(v) * 1e3, 3) for k, v in rr["per_k"].items()},
                      "roofline": dominant(rr, prec), "trace": rr["trace"],
                      "autotuned_ms_per_apply_by_k": [round(x, 3) for x in rr["tuned_ms"]],
-                     "variants": rr["variants"], "width2_with_passes": rr["passes"]}
+                     "variants": rr["variants"], "launches_per_step": rr["launches"],
+                     "passes_per_step": len(rr["pass_sizes"]) // max(a.steps, 1),
+                     "other_fusion_width": rr["alternative"]}
     if accuracy is not None:
         out["f32_vs_f64"] = accuracy
     if a.serve_requests > 0:

@@ -217,9 +217,11 @@ tanq_status tanq_variant_selected(int k, tanq_prec p, int* index);
  * unchanged), record the fastest of each width as the variant for (n, k, precision) -- it
  * takes precedence over the process-wide choice for states of n qubits until the next
  * tanq_variant_select of that (k, precision) -- and record the best milliseconds per apply.
- * TANQ_FUSE_AUTO then chooses the fusion width that minimises the sum of these costs over the
- * planned blocks.  ms_per_apply (may be NULL) receives 4 values, index k = 1..3 (0 where
- * k > n).  Synchronises. */
+ * Where passes apply (see tanq_set_pass_limit), also time passes of 2..limit superoperators on
+ * the four highest qubits and record milliseconds per pass.  TANQ_FUSE_AUTO then chooses the
+ * fusion width that minimises the sum of these costs over the launches tanq_apply_fused would
+ * make for each planned width.  ms_per_apply (may be NULL) receives 4 values, index k = 1..3
+ * (0 where k > n).  Synchronises. */
 tanq_status tanq_autotune(tanq_dm d, int reps, double* ms_per_apply);
 
 /* As tanq_autotune, but timed on dense data: d is first overwritten with the seeded
@@ -243,6 +245,11 @@ tanq_status tanq_get_pass_limit(int* max_superops);
  * of multi-superoperator passes and *in_passes the blocks they apply (the other blocks are
  * applied one by one).  Host only. */
 tanq_status tanq_fused_passes(tanq_fused f, int* passes, int* in_passes);
+/* The launches tanq_apply_fused makes for f, in order: run_len[i] blocks (1 = a single apply,
+ * >= 2 = a pass) starting where launch i - 1 ended.  *count receives the number of launches;
+ * run_len may be NULL to query it (E_ARG if cap is smaller).  Applying f launch by launch with
+ * tanq_apply_fused_range over these ranges gives the same launches.  Host only. */
+tanq_status tanq_fused_launches(tanq_fused f, int* run_len, int cap, int* count);
 /* Diagnostics of one pass layout (host only): m 2-qubit superoperators on n qubits, qubits =
  * m pairs; *conflict_free receives how many of the 2 m LDS access patterns (the MFMA operand
  * reads and the result writes of each superoperator) the chosen swizzle keeps free of bank
@@ -256,8 +263,9 @@ tanq_status tanq_variant_for(int n, int k, tanq_prec p, int* index);
 
 /* The autotuning cache as text, to keep tuning results across processes: one line per tuned
  * (n, k, precision), "tune <n> <k> <f64|f32> <tile_bits> <threads> <staging> <ms per apply>"
- * (tile bits, threads and staging are 0 for k = 1).  buf may be NULL to query; *len receives
- * the size needed, including the terminating NUL; E_ARG if cap is smaller. */
+ * (tile bits, threads and staging are 0 for k = 1), and one per timed pass length,
+ * "pass <n> <f64|f32> <superoperators> <ms per pass>".  buf may be NULL to query; *len
+ * receives the size needed, including the terminating NUL; E_ARG if cap is smaller. */
 tanq_status tanq_tuning_export(char* buf, size_t cap, size_t* len);
 /* Load text written by tanq_tuning_export (blank lines and lines starting with '#' are
  * skipped).  Every line is validated first -- E_ARG names a malformed line or a variant this

@@ -452,6 +452,20 @@ void cost_set(int n, tanq_prec p, int k, double ms) {
   g_cost_ms[n][p == TANQ_F64 ? 0 : 1][k] = ms;
 }
 
+// Measured milliseconds per multi-superoperator pass of m 2-qubit superoperators, per (n,
+// precision, m); guarded by g_cost_mu.
+double g_pass_ms[MAX_N + 1][2][kPassMax + 1] = {};
+
+double pass_cost_get(int n, tanq_prec p, int m) {
+  std::lock_guard<std::mutex> lk(g_cost_mu);
+  return g_pass_ms[n][p == TANQ_F64 ? 0 : 1][m];
+}
+
+void pass_cost_set(int n, tanq_prec p, int m, double ms) {
+  std::lock_guard<std::mutex> lk(g_cost_mu);
+  g_pass_ms[n][p == TANQ_F64 ? 0 : 1][m] = ms;
+}
+
 // Cost of one apply of width k, used to choose the fusion width when asked to: the
 // autotuned time if there is one for (n, precision), else a model in units of one HBM
 // pass over vec(rho) -- k <= 2 is bound by that pass, k = 3 by MFMA throughput (16 flop/B
@@ -461,6 +475,31 @@ double apply_cost(int n, int k, tanq_prec p) {
   if (ms > 0.0) return ms;
   if (k <= 2) return 1.0;
   return 1.65;
+}
+
+// Cost of one pass of m 2-qubit superoperators: the measured time if there is one, else the
+// 2-qubit apply cost scaled by a model of the pass (one HBM pass plus about a third of one
+// per additional superoperator, as measured in FP64 at 16 qubits).
+double pass_cost(int n, int m, tanq_prec p) {
+  const double ms = pass_cost_get(n, p, m);
+  if (ms > 0.0) return ms;
+  return apply_cost(n, 2, p) * (1.0 + 0.35 * (m - 1));
+}
+
+// Cost of applying a planned block list the way tanq_apply_fused does (passes included).
+double plan_cost(const std::vector<PlanBlock>& pl, int n, tanq_prec p) {
+  auto at = [&](int j, const int** q) {
+    *q = pl[j].qubits.data();
+    return (int)pl[j].qubits.size();
+  };
+  const int lim = pass_limit();
+  double c = 0.0;
+  for (int i = 0; i < (int)pl.size();) {
+    const int m = pass_run(at, i, (int)pl.size(), n, p, lim);
+    c += m >= 2 ? pass_cost(n, m, p) : apply_cost(n, (int)pl[i].qubits.size(), p);
+    i += m;
+  }
+  return c;
 }
 
 }  // namespace
@@ -480,8 +519,7 @@ tanq_status tanq_fuse(tanq_circuit c, int max_width, tanq_prec p, void* hip_stre
       double best = 1e300;
       for (int w = 2; w <= std::min(3, n); ++w) {
         std::vector<PlanBlock> pl = plan_fusion(pops, n, w);
-        double cost = 0.0;
-        for (auto& b : pl) cost += apply_cost(n, (int)b.qubits.size(), p);
+        const double cost = plan_cost(pl, n, p);
         if (cost < best) {
           best = cost;
           plan = std::move(pl);
@@ -754,6 +792,12 @@ tanq_status tanq_tuning_export(char* buf, size_t cap, size_t* len) {
                         st, ms);
           out += line;
         }
+        for (int m = 2; m <= kPassMax; ++m) {
+          const double ms = pass_cost_get(n, p, m);
+          if (!(ms > 0.0)) continue;
+          std::snprintf(line, sizeof(line), "pass %d %s %d %.6g\n", n, pi == 0 ? "f64" : "f32", m, ms);
+          out += line;
+        }
       }
     *len = out.size() + 1;
     if (buf) {
@@ -767,7 +811,7 @@ tanq_status tanq_tuning_import(const char* text) {
   return guarded([&] {
     if (!text) fail(TANQ_E_ARG, "text is NULL");
     struct Row {
-      int n, k, variant;
+      int n, k, variant;  // k = 0: a pass row, variant = superoperators per pass
       tanq_prec p;
       double ms;
     };
@@ -783,6 +827,18 @@ tanq_status tanq_tuning_import(const char* text) {
       char prec[8] = {0};
       int n = 0, k = 0, tb = 0, th = 0, st = 0;
       double ms = 0.0;
+      if (line.compare(0, 5, "pass ") == 0) {
+        int m = 0;
+        if (std::sscanf(line.c_str(), "pass %d %7s %d %lf", &n, prec, &m, &ms) != 4)
+          fail(TANQ_E_ARG, "tuning line " + std::to_string(lineno) + " is malformed");
+        const std::string ps(prec);
+        if (ps != "f64" && ps != "f32") fail(TANQ_E_ARG, "tuning line " + std::to_string(lineno) + ": bad precision");
+        const tanq_prec p = ps == "f64" ? TANQ_F64 : TANQ_F32;
+        if (n < 1 || n > MAX_N || m < 2 || m > pass_max(p) || !(ms > 0.0))
+          fail(TANQ_E_ARG, "tuning line " + std::to_string(lineno) + ": out of range");
+        rows.push_back({n, 0, m, p, ms});
+        continue;
+      }
       if (std::sscanf(line.c_str(), "tune %d %d %7s %d %d %d %lf", &n, &k, prec, &tb, &th, &st, &ms) != 7)
         fail(TANQ_E_ARG, "tuning line " + std::to_string(lineno) + " is malformed");
       const std::string ps(prec);
@@ -798,6 +854,10 @@ tanq_status tanq_tuning_import(const char* text) {
       rows.push_back({n, k, v, p, ms});
     }
     for (const Row& r : rows) {  // all lines valid: apply them
+      if (r.k == 0) {
+        pass_cost_set(r.n, r.p, r.variant, r.ms);
+        continue;
+      }
       if (r.k > 1) variant_tune(r.n, r.k, r.p, r.variant);
       cost_set(r.n, r.p, r.k, r.ms);
     }
@@ -901,6 +961,39 @@ static void autotune_impl(tanq_dm d, int reps, bool dense, double* ms_per_apply)
         best_ms[k] = best_t;
         cost_set(n, p, k, best_t);
       }
+      // passes of m 2-qubit superoperators on the four highest qubits (whole 128-byte runs),
+      // every superoperator the same identity (or dense unitary) operand
+      if (n >= 4 && 2 * n >= pass_tile_bits(p) && pass_limit() >= 2) {
+        const int D = 16;
+        std::vector<double> S((size_t)D * D * 2, 0.0);
+        if (dense)
+          S = dense_unitary_superop(2);
+        else
+          for (int a = 0; a < D; ++a) S[2 * ((size_t)a * D + a)] = 1.0;
+        TANQ_HIP(hipStreamSynchronize(d->stream));
+        TANQ_HIP(hipMemcpy(d->s_raw_dev, S.data(), S.size() * sizeof(double), hipMemcpyHostToDevice));
+        launch_pack_one(2, d->s_raw_dev, d->s_packed_dev, p, d->stream);
+        const int a = n - 4, b = n - 3, c = n - 2, e = n - 1;
+        const int cyc[6][2] = {{a, b}, {c, e}, {a, c}, {b, e}, {a, e}, {b, c}};
+        const int mmax = std::min(pass_limit(), pass_max(p));
+        for (int m = 2; m <= mmax; ++m) {
+          int q[2 * kPassMax];
+          uint32_t off[kPassMax] = {0};
+          for (int t = 0; t < m; ++t) {
+            q[2 * t] = cyc[t % 6][0];
+            q[2 * t + 1] = cyc[t % 6][1];
+          }
+          const PassGeom pg = make_pass_geom(n, m, q, off, p);
+          launch_pass(d->ptr, p, pg, d->s_packed_dev, d->stream);  // warm-up
+          TANQ_HIP(hipEventRecord(e0, d->stream));
+          for (int r = 0; r < 2 * reps; ++r) launch_pass(d->ptr, p, pg, d->s_packed_dev, d->stream);
+          TANQ_HIP(hipEventRecord(e1, d->stream));
+          TANQ_HIP(hipEventSynchronize(e1));
+          float ms = 0.f;
+          TANQ_HIP(hipEventElapsedTime(&ms, e0, e1));
+          pass_cost_set(n, p, m, (double)ms / (2.0 * reps));
+        }
+      }
   } catch (...) {
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -943,6 +1036,29 @@ tanq_status tanq_fused_passes(tanq_fused f, int* passes, int* in_passes) {
     }
     *passes = np;
     *in_passes = nin;
+  });
+}
+
+tanq_status tanq_fused_launches(tanq_fused f, int* run_len, int cap, int* count) {
+  return guarded([&] {
+    if (!f || !count) fail(TANQ_E_ARG, "NULL argument");
+    const int lim = pass_limit();
+    auto at = [&](int j, const int** q) {
+      *q = f->blocks[j].qubits;
+      return f->blocks[j].k;
+    };
+    std::vector<int> runs;
+    const int end = (int)f->blocks.size();
+    for (int i = 0; i < end;) {
+      const int m = pass_run(at, i, end, f->n, f->prec, lim);
+      runs.push_back(m);
+      i += m;
+    }
+    *count = (int)runs.size();
+    if (run_len) {
+      if (cap < (int)runs.size()) fail(TANQ_E_ARG, "run_len too small");
+      std::copy(runs.begin(), runs.end(), run_len);
+    }
   });
 }
 

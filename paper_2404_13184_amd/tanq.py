@@ -43,6 +43,7 @@ EXPORTED = [
     "tanq_variant_count", "tanq_variant_get", "tanq_variant_select", "tanq_variant_selected", "tanq_autotune",
     "tanq_variant_for", "tanq_tuning_export", "tanq_tuning_import", "tanq_autotune_dense",
     "tanq_set_pass_limit", "tanq_get_pass_limit", "tanq_pass_layout_info", "tanq_fused_passes",
+    "tanq_fused_launches",
     "tanq_probs", "tanq_probs_readout", "tanq_sample", "tanq_dm_set_basis", "tanq_reduced_dm",
     "tanq_process_chi_1q",
     "tanq_expect_pauli", "tanq_expect_pauli_c", "tanq_expect_pauli_batch",
@@ -140,6 +141,7 @@ _SIGS = {
     "tanq_get_pass_limit": ([_ip], ctypes.c_int),
     "tanq_pass_layout_info": ([ctypes.c_int, ctypes.c_int, _ip, ctypes.c_int, _ip], ctypes.c_int),
     "tanq_fused_passes": ([_vp, _ip, _ip], ctypes.c_int),
+    "tanq_fused_launches": ([_vp, _ip, ctypes.c_int, _ip], ctypes.c_int),
     "tanq_tuning_export": ([ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "tanq_tuning_import": ([ctypes.c_char_p], ctypes.c_int),
     "tanq_reduced_dm": ([_vp, ctypes.c_int, _ip, _dp], ctypes.c_int),
@@ -419,6 +421,15 @@ def tanq_fused_passes(h: int):
     a, b = ctypes.c_int(), ctypes.c_int()
     _check(load().tanq_fused_passes(h, ctypes.byref(a), ctypes.byref(b)))
     return a.value, b.value
+
+
+def tanq_fused_launches(h: int) -> List[int]:
+    """Blocks per launch of tanq_apply_fused for a fused list (1 = single apply, >= 2 = pass)."""
+    cnt = ctypes.c_int()
+    _check(load().tanq_fused_launches(h, None, 0, ctypes.byref(cnt)))
+    buf = (ctypes.c_int * max(cnt.value, 1))()
+    _check(load().tanq_fused_launches(h, buf, cnt.value, ctypes.byref(cnt)))
+    return list(buf[:cnt.value])
 
 
 def tanq_pass_layout_info(n: int, pairs: Sequence[Sequence[int]], prec) -> int:
@@ -716,6 +727,10 @@ class Fused:
     def passes(self):
         """(passes, blocks inside passes) that apply_fused uses under the current pass limit."""
         return tanq_fused_passes(self.h)
+
+    def launches(self) -> List[int]:
+        """Blocks per launch of apply_fused, in order (1 = single apply, >= 2 = pass)."""
+        return tanq_fused_launches(self.h)
 
     def get_k(self, idx: int) -> int:
         if getattr(self, "_ks", None) is None:

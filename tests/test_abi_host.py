@@ -121,7 +121,7 @@ def test_tuning_cache_roundtrip(lib):
     P = T.TANQ_F32
     vs = [T.tanq_variant_get(3, P, i) for i in range(T.tanq_variant_count(3, P))]
     last = vs[-1]
-    text = "# cache\n\ntune 12 3 f32 %d %d %d 1.25\ntune 12 1 f32 0 0 0 0.5\n" % (
+    text = "# cache\n\ntune 12 3 f32 %d %d %d 1.25\ntune 12 1 f32 0 0 0 0.5\npass 12 f32 4 0.75\n" % (
         last["tile_bits"], last["threads"], last["staging"])
     T.tanq_tuning_import(text)
     try:
@@ -130,9 +130,11 @@ def test_tuning_cache_roundtrip(lib):
         out = T.tanq_tuning_export()
         assert "tune 12 3 f32 %d %d %d 1.25\n" % (last["tile_bits"], last["threads"], last["staging"]) in out
         assert "tune 12 1 f32 0 0 0 0.5\n" in out
+        assert "pass 12 f32 4 0.75\n" in out
         # all-or-nothing: a bad line anywhere leaves the tables unchanged
         for bad in ("tune 12 3 f32 99 64 0 1.0\n", "tune 12 3 f16 12 512 0 1.0\n", "tune 40 2 f64 10 256 0 1.0\n",
-                    "tune 12 2 f64 10 256 0\n", "tune 2 3 f64 12 512 0 1.0\n", "tune 12 2 f64 10 256 7 1.0\n"):
+                    "tune 12 2 f64 10 256 0\n", "tune 2 3 f64 12 512 0 1.0\n", "tune 12 2 f64 10 256 7 1.0\n",
+                    "pass 12 f64 9 1.0\n", "pass 12 f64 1 1.0\n", "pass 12 f16 2 1.0\n", "pass 12 f32 2\n"):
             with pytest.raises(T.TanqError):
                 T.tanq_tuning_import("tune 13 3 f32 %d %d %d 2.0\n" % (vs[0]["tile_bits"], vs[0]["threads"],
                                                                         vs[0]["staging"]) + bad)

@@ -107,3 +107,41 @@ def test_passes_bitwise_12_qubits(prec):
     got, (np_, _) = run_fused(n, ops, prec, 8)
     assert np_ > 0
     assert np.array_equal(got.view(np.uint8), want.view(np.uint8))
+
+
+def test_launch_ranges_reproduce_apply_fused():
+    """tanq_fused_launches lists the launches of tanq_apply_fused; replaying them range by range
+    gives the same bits (the benchmark times launches this way)."""
+    n = 8
+    ops = W.random_u3_cx(n, 5, 31, 1e-3, 1e-2)
+    c = T.Circuit(n, ops)
+    for prec in ("f64", "f32"):
+        say("launch ranges %s" % prec)
+        f = c.fuse(2, prec)
+        runs = f.launches()
+        np_, nin = f.passes()
+        assert sum(runs) == f.count and np_ > 0
+        assert sum(1 for r in runs if r >= 2) == np_ and sum(r for r in runs if r >= 2) == nin
+        d1, d2 = T.DM(n, prec), T.DM(n, prec)
+        d1.apply_fused(f)
+        pos = 0
+        for r in runs:
+            d2.apply_fused(f, pos, pos + r)
+            pos += r
+        assert np.array_equal(d1.read().view(np.uint8), d2.read().view(np.uint8))
+        d1.free()
+        d2.free()
+        f.free()
+    c.free()
+
+
+def test_autotune_times_passes():
+    for prec, mmax in (("f64", 3), ("f32", 8)):
+        say("autotune passes %s" % prec)
+        d = T.DM(8, prec)
+        d.autotune(reps=1)
+        out = T.tanq_tuning_export()
+        for m in range(2, mmax + 1):
+            assert "pass 8 %s %d " % (prec, m) in out
+        assert "pass 8 %s %d " % (prec, mmax + 1) not in out
+        d.free()
