@@ -236,9 +236,10 @@ tanq_status tanq_autotune_dense(tanq_dm d, int reps, double* ms_per_apply);
  * every tile of the state is read into LDS once, multiplied by each superoperator of the run in
  * circuit order (the same per-group arithmetic as a single apply, so the results are bitwise
  * those of applying the blocks one by one), and written back once.  This cuts HBM traffic, the
- * bound of 2-qubit applies (Sec. 3.2: a 2-qubit superoperator is memory-bound).  A pass needs
- * 2n >= 12 (FP64) or 13 (FP32) bits of state.  The limit is the most superoperators per pass,
- * 1..8 (1 = no passes; default 8), process-wide. */
+ * bound of 2-qubit applies (Sec. 3.2: a 2-qubit superoperator is memory-bound).  Passes are
+ * used on states of at least 10 (FP64) or 11 (FP32) qubits, for runs whose tiles keep whole
+ * 128-byte lines of vec(rho), with at most 3 (FP64) or 8 (FP32) superoperators.  The limit is
+ * the most superoperators per pass, 1..8 (1 = no passes; default 8), process-wide. */
 tanq_status tanq_set_pass_limit(int max_superops);
 tanq_status tanq_get_pass_limit(int* max_superops);
 /* How tanq_apply_fused groups f's blocks under the current limit: *passes receives the number

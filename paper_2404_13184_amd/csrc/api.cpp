@@ -177,6 +177,8 @@ void parse_pauli(int n, const char* s, uint64_t out[3]) {
 
 }  // namespace
 
+constexpr int kPassMinTileBits = 8;  // passes need at least 2^8 tiles (one per CU)
+
 // Contiguous elements (log2) of a pass tile in vec(rho): the tile holds the row and column bit
 // of every qubit in `qmask` plus the lowest other bits up to V; the low run is the number of
 // consecutive held bits from bit 0.  -1 if the qubits do not fit.
@@ -204,7 +206,9 @@ int pass_run(BlockAt at, int i, int end, int n, tanq_prec p, int lim) {
   const int V = pass_tile_bits(p);
   const int min_run = p == TANQ_F64 ? 3 : 4;  // 8 x 16 B or 16 x 8 B
   lim = std::min(lim, pass_max(p));
-  if (lim < 2 || 2 * n < V) return 1;
+  // smaller states (fewer pass tiles than CUs) are bound by launch and set-up costs, where
+  // single applies with their smaller tiles do better
+  if (lim < 2 || 2 * n - V < kPassMinTileBits) return 1;
   const int* q = nullptr;
   if (at(i, &q) != 2) return 1;
   uint64_t mask = (1ull << q[0]) | (1ull << q[1]);
@@ -963,7 +967,7 @@ static void autotune_impl(tanq_dm d, int reps, bool dense, double* ms_per_apply)
       }
       // passes of m 2-qubit superoperators on the four highest qubits (whole 128-byte runs),
       // every superoperator the same identity (or dense unitary) operand
-      if (n >= 4 && 2 * n >= pass_tile_bits(p) && pass_limit() >= 2) {
+      if (2 * n - pass_tile_bits(p) >= kPassMinTileBits && pass_limit() >= 2) {
         const int D = 16;
         std::vector<double> S((size_t)D * D * 2, 0.0);
         if (dense)

@@ -3,8 +3,8 @@
 Each pass performs, per superoperator, the same per-group MFMA sequence as a single apply, so
 the state after tanq_apply_fused with passes must equal, bit for bit, the state with passes
 switched off (limit 1); FP64 must also match the CPU oracle within 1e-10.  Sizes: the smallest
-states that hold a pass tile (n = 6 in FP64, n = 7 in FP32), a mid size, and a 12-qubit state
-compared on every element.  Circuits: the random U3/CX circuit (random pairs, so passes mix
+states that use passes (n = 10 in FP64, n = 11 in FP32: at least 256 pass tiles) and a
+12-qubit state, compared on every element.  Circuits: the random U3/CX circuit (random pairs, so passes mix
 low and high qubits) and the nearest-neighbour brickwork (passes on neighbouring qubits, low
 qubits inside the bank window)."""
 import sys
@@ -48,7 +48,7 @@ def circuits(n):
             ("brick", W.brickwork_cz(n, 6, 7 + n, 1e-3, 1e-2, 1e-3))]
 
 
-@pytest.mark.parametrize("prec,n", [("f64", 6), ("f64", 8), ("f32", 7), ("f32", 8)])
+@pytest.mark.parametrize("prec,n", [("f64", 10), ("f64", 11), ("f32", 11)])
 def test_passes_bitwise_equal_to_single_applies(prec, n):
     for name, ops in circuits(n):
         say("passes %s n=%d %s" % (prec, n, name))
@@ -61,7 +61,7 @@ def test_passes_bitwise_equal_to_single_applies(prec, n):
 
 @pytest.mark.parametrize("limit", [2, 3, 5])
 def test_pass_limits(limit):
-    n = 8
+    n = 10
     ops = W.random_u3_cx(n, 5, 3, 1e-3, 1e-2)
     say("pass limit %d" % limit)
     want, _ = run_fused(n, ops, "f64", 1)
@@ -71,7 +71,7 @@ def test_pass_limits(limit):
 
 
 def test_passes_match_oracle_f64(oracle_mod):
-    n = 7
+    n = 10
     for name, ops in circuits(n):
         say("passes vs oracle n=%d %s" % (n, name))
         got, (np_, _) = run_fused(n, ops, "f64", 8)
@@ -82,13 +82,13 @@ def test_passes_match_oracle_f64(oracle_mod):
 
 def test_passes_on_a_dense_input_f32(oracle_mod):
     """FP32 against the FP64 oracle from a dense random state (every element nonzero)."""
-    n = 7
+    n = 11
     rng = np.random.default_rng(5)
     A = rng.standard_normal((1 << n, 1 << n)) + 1j * rng.standard_normal((1 << n, 1 << n))
     rho = A @ A.conj().T
     rho /= np.trace(rho)
     vec = oracle_mod.matrix_to_vec(rho)
-    ops = W.random_u3_cx(n, 4, 21, 1e-3, 1e-2)
+    ops = W.random_u3_cx(n, 2, 21, 1e-3, 1e-2)
     say("passes f32 dense n=%d" % n)
     got, (np_, _) = run_fused(n, ops, "f32", 8, rho_in=vec.astype(np.complex64))
     assert np_ > 0
@@ -112,7 +112,7 @@ def test_passes_bitwise_12_qubits(prec):
 def test_launch_ranges_reproduce_apply_fused():
     """tanq_fused_launches lists the launches of tanq_apply_fused; replaying them range by range
     gives the same bits (the benchmark times launches this way)."""
-    n = 8
+    n = 11
     ops = W.random_u3_cx(n, 5, 31, 1e-3, 1e-2)
     c = T.Circuit(n, ops)
     for prec in ("f64", "f32"):
@@ -138,10 +138,10 @@ def test_launch_ranges_reproduce_apply_fused():
 def test_autotune_times_passes():
     for prec, mmax in (("f64", 3), ("f32", 8)):
         say("autotune passes %s" % prec)
-        d = T.DM(8, prec)
+        d = T.DM(11, prec)
         d.autotune(reps=1)
         out = T.tanq_tuning_export()
         for m in range(2, mmax + 1):
-            assert "pass 8 %s %d " % (prec, m) in out
-        assert "pass 8 %s %d " % (prec, mmax + 1) not in out
+            assert "pass 11 %s %d " % (prec, m) in out
+        assert "pass 11 %s %d " % (prec, mmax + 1) not in out
         d.free()
