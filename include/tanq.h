@@ -254,9 +254,11 @@ tanq_status tanq_fused_launches(tanq_fused f, int* run_len, int cap, int* count)
 /* Diagnostics of one pass layout (host only): m 2-qubit superoperators on n qubits, qubits =
  * m pairs; *conflict_free receives how many of the 2 m LDS access patterns (the MFMA operand
  * reads and the result writes of each superoperator) the chosen swizzle keeps free of bank
- * conflicts.  E_ARG if the pass is not valid (qubits out of range or repeated within a block,
- * more than 6 distinct qubits, m outside 1..8, too small a state). */
-tanq_status tanq_pass_layout_info(int n, int m, const int* qubits, tanq_prec p, int* conflict_free);
+ * conflicts, *achievable an upper bound of that number over all swizzles of the kernels' form
+ * (in FP32 a pattern can be conflict-free only if its lowest free bits include tile bit 0).
+ * E_ARG if the pass is not valid (qubits out of range or repeated within a block, more than 6
+ * distinct qubits, m outside 1..8, too small a state). */
+tanq_status tanq_pass_layout_info(int n, int m, const int* qubits, tanq_prec p, int* conflict_free, int* achievable);
 
 /* The variant applies of width k on n-qubit states use (the autotuned one, else the
  * process-wide choice). */

@@ -1066,15 +1066,17 @@ tanq_status tanq_fused_launches(tanq_fused f, int* run_len, int cap, int* count)
   });
 }
 
-tanq_status tanq_pass_layout_info(int n, int m, const int* qubits, tanq_prec p, int* conflict_free) {
+tanq_status tanq_pass_layout_info(int n, int m, const int* qubits, tanq_prec p, int* conflict_free,
+                                  int* achievable) {
   return guarded([&] {
-    if (!qubits || !conflict_free) fail(TANQ_E_ARG, "NULL argument");
+    if (!qubits || !conflict_free || !achievable) fail(TANQ_E_ARG, "NULL argument");
     check_prec(p);
     if (n < 1 || n > MAX_N) fail(TANQ_E_ARG, "n out of range");
     uint32_t off[kPassMax] = {0};
-    int score = 0;
-    (void)make_pass_geom(n, m, qubits, off, p, &score);
+    int score = 0, bound = 0;
+    (void)make_pass_geom(n, m, qubits, off, p, &score, &bound);
     *conflict_free = score;
+    *achievable = bound;
   });
 }
 

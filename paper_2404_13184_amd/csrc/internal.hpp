@@ -145,9 +145,10 @@ int pass_tile_bits(tanq_prec p);
 // Most superoperators one pass of precision p holds (at most kPassMax).
 int pass_max(tanq_prec p);
 // conflict_free (optional): access patterns (two per superoperator) whose LDS reads and writes
-// are free of bank conflicts under the chosen swizzle.
+// are free of bank conflicts under the chosen swizzle; achievable (optional): an upper bound of
+// that count over all swizzles of this form.
 PassGeom make_pass_geom(int n, int m, const int* qubits, const uint32_t* op_off, tanq_prec p,
-                        int* conflict_free = nullptr);
+                        int* conflict_free = nullptr, int* achievable = nullptr);
 void launch_pass(void* rho, tanq_prec p, const PassGeom& g, const void* frags, hipStream_t s);
 // Process-wide limit on superoperators per pass (1 = no passes).
 int pass_limit();

@@ -18,6 +18,11 @@
 // superoperator, the 16 groups an MFMA column block reads land on distinct banks (and, for FP32,
 // also the two rows each lane pair covers); by linearity S(tile index of a target part + group
 // part) = S(target part) ^ S(group part), so the target offsets are swizzled once on the host.
+// In FP32 X never flips bit 0, so the two elements of a 16-byte slot stay in order.
+//
+// Kernel.  One workgroup per CU with specialised waves: producer waves stream the next tile into
+// one of two LDS buffers with direct global-to-LDS loads while consumer waves multiply the
+// current tile in the other and store it (see apply_pass_ws_kernel).
 #include <atomic>
 #include <cstring>
 
@@ -53,167 +58,40 @@ __device__ inline uint64_t pass_tile_base(const PassGeom& g, uint64_t tile) {
 
 }  // namespace
 
-// Persistent grid over full tiles (2^VMAX elements); the next tile is prefetched into registers
-// while the current one goes through the pass, as in the single-superoperator kernel.
-template <typename T, int VMAX, int NT>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void apply_pass_kernel(T* __restrict__ rho, const T* __restrict__ frags,
-                                                        const PassGeom g) {
-  using M = Mfma<T>;
-  using acc_t = typename M::acc_t;
-  using c2 = typename M::c2;
-  constexpr int EPS = 16 / (2 * (int)sizeof(T));  // elements per 16-byte slot
-  constexpr int SLOTS = (1 << VMAX) / EPS;
-  constexpr int ITERS = SLOTS / NT;
-  static_assert(SLOTS % NT == 0, "whole slots per thread");
-  constexpr int NW = NT / 64;
-  constexpr int NB = (1 << (VMAX - 4)) / 16;  // 16-group column blocks per superoperator
-  constexpr int NBW = NB / NW;
-  static_assert(NB % NW == 0, "every wave gets the same number of column blocks");
-  constexpr int MT = 2, KS = 8;
+// Superoperators per specialised-wave pass: their operands (1024 elements each) live in LDS
+// beside the two 64 KiB tile buffers.
+template <typename T>
+struct PassWsMax;
+template <>
+struct PassWsMax<double> { static constexpr int M = 3; };
+template <>
+struct PassWsMax<float> { static constexpr int M = 4; };
 
-  constexpr int G = 1 << (VMAX - 4);  // groups of one superoperator in a tile
-  __shared__ u32x4 lds[SLOTS];
-  // swizzled tile index of group gi of superoperator j (the same for every tile)
-  __shared__ uint16_t gxt[kPassMax][G];
-  T* ldsT = reinterpret_cast<T*>(lds);
-
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int kk = lane >> 4;  // B row within a k-step
-  const int cc = kk & 1;     // re / im of that row
-  const int hb = kk >> 1;    // low complex bit of that row
-
-  // FP32 moves two elements per 16-byte slot; the swizzle keeps them in one slot (X does not
-  // depend on bit 0) but may swap their order, which the load and store phases undo
-  uint64_t off[ITERS];
-  uint32_t lslot[ITERS];
-  bool swap[ITERS];
-#pragma unroll
-  for (int it = 0; it < ITERS; ++it) {
-    const uint32_t j = (uint32_t)((it * NT + tid) * EPS);
-    uint64_t o = 0;
-    for (int b = 0; b < VMAX; ++b) o |= (uint64_t)((j >> b) & 1u) << g.vpos[b];
-    off[it] = o;
-    const uint32_t sj = pass_swz<T>(j, g);
-    lslot[it] = sj / EPS;
-    swap[it] = EPS == 2 && ((sj ^ j) & 1u);
-  }
-  auto order = [&](u32x4 v, int it) { return swap[it] ? u32x4{v[2], v[3], v[0], v[1]} : v; };
-
-  uint64_t tile = xcd_first_tile();
-  if (tile >= g.ntiles) return;  // uniform per workgroup
-  for (int idx = tid; idx < g.m * G; idx += NT) {
-    const int j = idx / G, gi = idx % G;
-    gxt[j][gi] = (uint16_t)pass_swz<T>(pdep32((uint32_t)gi, g.free_mask[j]), g);
-  }
-  uint64_t cur = pass_tile_base(g, tile);
-  u32x4 buf[ITERS];
-#pragma unroll
-  for (int it = 0; it < ITERS; ++it) buf[it] = *reinterpret_cast<const u32x4*>(rho + 2 * (cur + off[it]));
-#pragma unroll
-  for (int it = 0; it < ITERS; ++it) lds[lslot[it]] = order(buf[it], it);
-  lds_barrier();
-
-  for (;;) {
-    const uint64_t next = tile + gridDim.x;
-    const bool more = next < g.ntiles;
-    uint64_t nbase = 0;
-    if (more) {
-      nbase = pass_tile_base(g, next);
-#pragma unroll
-      for (int it = 0; it < ITERS; ++it) buf[it] = *reinterpret_cast<const u32x4*>(rho + 2 * (nbase + off[it]));
-    }
-
-    for (int j = 0; j < g.m; ++j) {
-      T afr[MT][KS];
-      const T* fr = frags + g.op_off[j];
-#pragma unroll
-      for (int m = 0; m < MT; ++m)
-#pragma unroll
-        for (int s = 0; s < KS; ++s) afr[m][s] = fr[(m * KS + s) * 64 + lane];
-      const uint32_t* st = g.stj[j];
-      const uint32_t s1 = hb ? st[1] : 0u;
-#pragma unroll
-      for (int i = 0; i < NBW; ++i) {
-        const uint32_t gx = gxt[j][(wave + i * NW) * 16 + (lane & 15)];
-        acc_t acc[MT];
-#pragma unroll
-        for (int m = 0; m < MT; ++m) acc[m] = acc_t{0, 0, 0, 0};
-#pragma unroll
-        for (int s = 0; s < KS; ++s) {
-          const uint32_t e = (st[2 * s] ^ s1) ^ gx;
-          const T b = ldsT[2 * e + cc];
-#pragma unroll
-          for (int m = 0; m < MT; ++m) acc[m] = M::mma(afr[m][s], b, acc[m]);
-        }
-        // a wave writes only the groups it read, so no barrier inside one superoperator
-#pragma unroll
-        for (int m = 0; m < MT; ++m) {
-          if constexpr (M::kRowsStrided) {
-            // value r = real row kk + 4r of m-tile m: component cc of output a = 8m + 2r + hb
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              const uint32_t e = (st[8 * m] ^ st[2 * r] ^ s1) ^ gx;
-              ldsT[2 * e + cc] = acc[m][r];
-            }
-          } else {
-            // values (0,1), (2,3) = (re, im) of outputs a = 8m + 2kk and a + 1
-            const uint32_t tq = ((kk & 1) ? st[2] : 0u) ^ ((kk & 2) ? st[4] : 0u);
-            const uint32_t e0 = (st[8 * m] ^ tq) ^ gx;
-            const uint32_t e1 = e0 ^ st[1];
-            *reinterpret_cast<c2*>(ldsT + 2 * e0) = c2{acc[m][0], acc[m][1]};
-            *reinterpret_cast<c2*>(ldsT + 2 * e1) = c2{acc[m][2], acc[m][3]};
-          }
-        }
-      }
-      lds_barrier();  // the next superoperator reads groups other waves wrote
-    }
-
-#pragma unroll
-    for (int it = 0; it < ITERS; ++it) *reinterpret_cast<u32x4*>(rho + 2 * (cur + off[it])) = order(lds[lslot[it]], it);
-    if (!more) break;
-    lds_barrier();  // every store-phase LDS read is done before the next tile lands
-#pragma unroll
-    for (int it = 0; it < ITERS; ++it) lds[lslot[it]] = order(buf[it], it);
-    lds_barrier();
-    tile = next;
-    cur = nbase;
-  }
-}
-
-// FP64 passes with specialised waves, one workgroup per CU.  NPW producer waves stream the next
-// tile into one of two LDS buffers with direct global-to-LDS loads while NCW consumer waves
-// multiply the current tile in the other and store it.  The roles run separate loops, so the
-// consumers' LDS reads are never preceded by a global-to-LDS load in their own instruction
-// stream (the compiler would otherwise wait for every such load before the first read).  Both
-// loops execute the same barriers, in the same order, per tile (all counts are uniform):
-//   B0 (tile ready) -- m barriers, one after each superoperator -- B_free (buffer read out);
-// the producer issues the next tile's loads right after B0 and waits for them before the next
-// B0, so they stream during the whole multiplication and store of the current tile.
-constexpr int kPassWsMax = 3;  // superoperators per FP64 pass (their operands live in LDS)
-
-// Global offset of the tile element held by LDS slot p (S is an involution: slot p holds S(p)).
-template <int VMAX>
-__device__ inline uint64_t pass_slot_off(uint32_t p, const PassGeom& g) {
-  const uint32_t e = pass_swz<double>(p, g);
+// Global offset of tile element e0 = S(first element of LDS slot p); the slot's EPS elements are
+// consecutive in the tile and in vec(rho) (tile bit 0 is global bit 0, and this swizzle never
+// flips bit 0 for FP32, so a slot's pair keeps its order).
+template <typename T, int VMAX>
+__device__ inline uint64_t pass_slot_off(uint32_t first, const PassGeom& g) {
+  const uint32_t e = pass_swz<T>(first, g);
   uint64_t o = 0;
   for (int b = 0; b < VMAX; ++b) o |= (uint64_t)((e >> b) & 1u) << g.vpos[b];
   return o;
 }
 
-// One superoperator of an FP64 pass on the tile in ldsT, by consumer wave cw of NCW.
-template <int VMAX, int NCW>
-__device__ inline void pass_superop_f64(double* ldsT, const double (*opl)[1024], const uint16_t (*gxt)[1 << (VMAX - 4)],
-                                        const PassGeom& g, int j, int cw, int lane) {
-  using M = Mfma<double>;
+// One superoperator of a pass on the tile in ldsT, by consumer wave cw of NCW: the same
+// real-block MFMA sequence as the single apply (Op2), with the pass's swizzled offsets.
+template <typename T, int VMAX, int NCW>
+__device__ inline void pass_superop(T* ldsT, const T (*opl)[1024], const uint16_t (*gxt)[1 << (VMAX - 4)],
+                                    const PassGeom& g, int j, int cw, int lane) {
+  using M = Mfma<T>;
   using acc_t = typename M::acc_t;
+  using c2 = typename M::c2;
   constexpr int NB = (1 << (VMAX - 4)) / 16;
   constexpr int NBW = NB / NCW;
   static_assert(NB % NCW == 0, "every consumer wave gets the same number of column blocks");
   constexpr int MT = 2, KS = 8;
   const int kk = lane >> 4, cc = kk & 1, hb = kk >> 1;
-  double afr[MT][KS];
+  T afr[MT][KS];
 #pragma unroll
   for (int m = 0; m < MT; ++m)
 #pragma unroll
@@ -228,43 +106,59 @@ __device__ inline void pass_superop_f64(double* ldsT, const double (*opl)[1024],
     for (int m = 0; m < MT; ++m) acc[m] = acc_t{0, 0, 0, 0};
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
-      const double bv = ldsT[2 * ((st[2 * s] ^ s1) ^ gx) + cc];
+      const T bv = ldsT[2 * ((st[2 * s] ^ s1) ^ gx) + cc];
 #pragma unroll
       for (int m = 0; m < MT; ++m) acc[m] = M::mma(afr[m][s], bv, acc[m]);
     }
     // a wave writes only the groups it read, so no barrier inside one superoperator
 #pragma unroll
-    for (int m = 0; m < MT; ++m)
+    for (int m = 0; m < MT; ++m) {
+      if constexpr (M::kRowsStrided) {
+        // value r = real row kk + 4r of m-tile m: component cc of output a = 8m + 2r + hb
 #pragma unroll
-      for (int r = 0; r < 4; ++r) ldsT[2 * ((st[8 * m] ^ st[2 * r] ^ s1) ^ gx) + cc] = acc[m][r];
+        for (int r = 0; r < 4; ++r) ldsT[2 * ((st[8 * m] ^ st[2 * r] ^ s1) ^ gx) + cc] = acc[m][r];
+      } else {
+        // values (0,1), (2,3) = (re, im) of outputs a = 8m + 2kk and a + 1
+        const uint32_t tq = ((kk & 1) ? st[2] : 0u) ^ ((kk & 2) ? st[4] : 0u);
+        const uint32_t e0 = (st[8 * m] ^ tq) ^ gx;
+        *reinterpret_cast<c2*>(ldsT + 2 * e0) = c2{acc[m][0], acc[m][1]};
+        *reinterpret_cast<c2*>(ldsT + 2 * (e0 ^ st[1])) = c2{acc[m][2], acc[m][3]};
+      }
+    }
   }
 }
 
 // Producer: stream one tile into buf with direct global-to-LDS loads (lane data lands at the
-// wave's base + 16 * lane, so slot it * PT + tid receives the element at offset off[it]).
-template <int PITERS, int PT>
-__device__ inline void pass_dma_tile(const double* rho, uint64_t base, const uint64_t (&off)[PITERS], u32x4* buf,
+// wave's base + 16 * lane, so slot it * PT + tid receives the 16 bytes at offset off[it]).
+template <typename T, int PITERS, int PT>
+__device__ inline void pass_dma_tile(const T* rho, uint64_t base, const uint64_t (&off)[PITERS], u32x4* buf,
                                      int wave) {
 #pragma unroll
   for (int it = 0; it < PITERS; ++it)
     __builtin_amdgcn_global_load_lds(rho + 2 * (base + off[it]), buf + it * PT + wave * 64, 16, 0, 0);
 }
 
-template <int VMAX, int NT, int NPW>
-__global__ __launch_bounds__(NT) void apply_pass_ws_kernel(double* __restrict__ rho, const double* __restrict__ frags,
+template <typename T, int VMAX, int NT, int NPW>
+__global__ __launch_bounds__(NT) void apply_pass_ws_kernel(T* __restrict__ rho, const T* __restrict__ frags,
                                                            const PassGeom g) {
   constexpr int NCW = NT / 64 - NPW;
-  constexpr int SLOTS = 1 << VMAX;             // one FP64 complex element per 16-byte slot
+  constexpr int EPS = 16 / (2 * (int)sizeof(T));  // elements per 16-byte slot
+  constexpr int SLOTS = (1 << VMAX) / EPS;
   constexpr int PT = NPW * 64, CT = NCW * 64;  // producer and consumer threads
   constexpr int PITERS = SLOTS / PT;           // loads per producer lane per tile
   constexpr int CITERS = SLOTS / CT;           // stores per consumer thread per tile
   static_assert(SLOTS % PT == 0 && SLOTS % CT == 0, "whole slots per thread");
   constexpr int G = 1 << (VMAX - 4);
+  constexpr int MMAX = PassWsMax<T>::M;
 
   __shared__ u32x4 ldsA[SLOTS];
   __shared__ u32x4 ldsB[SLOTS];
-  __shared__ double opl[kPassWsMax][1024];
-  __shared__ uint16_t gxt[kPassWsMax][G];
+  __shared__ T opl[MMAX][1024];
+  __shared__ uint16_t gxt[MMAX][G];
+  // base offset of the tile in each buffer, written by the producer with its loads: the
+  // consumers take it from LDS rather than recomputing it from the run table (which the
+  // compiler may read with vector loads, and waiting for those would wait for the stores)
+  __shared__ uint64_t tbase[2];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -275,7 +169,7 @@ __global__ __launch_bounds__(NT) void apply_pass_ws_kernel(double* __restrict__ 
   for (int idx = tid; idx < g.m * 1024; idx += NT) opl[idx >> 10][idx & 1023] = frags[g.op_off[idx >> 10] + (idx & 1023)];
   for (int idx = tid; idx < g.m * G; idx += NT) {
     const int j = idx / G, gi = idx % G;
-    gxt[j][gi] = (uint16_t)pass_swz<double>(pdep32((uint32_t)gi, g.free_mask[j]), g);
+    gxt[j][gi] = (uint16_t)pass_swz<T>(pdep32((uint32_t)gi, g.free_mask[j]), g);
   }
   lds_barrier();  // operands and table in place before the roles split
 
@@ -283,14 +177,23 @@ __global__ __launch_bounds__(NT) void apply_pass_ws_kernel(double* __restrict__ 
     // ---------------- producer ----------------
     uint64_t off[PITERS];
 #pragma unroll
-    for (int it = 0; it < PITERS; ++it) off[it] = pass_slot_off<VMAX>((uint32_t)(it * PT + tid), g);
-    pass_dma_tile<PITERS, PT>(rho, pass_tile_base(g, tile), off, ldsA, wave);
+    for (int it = 0; it < PITERS; ++it) off[it] = pass_slot_off<T, VMAX>((uint32_t)((it * PT + tid) * EPS), g);
+    {
+      const uint64_t base = pass_tile_base(g, tile);
+      if (tid == 0) tbase[0] = base;
+      pass_dma_tile<T, PITERS, PT>(rho, base, off, ldsA, wave);
+    }
     vm_wait<0>();
     raw_barrier();  // B0: first tile ready
     for (int t = 0;; ++t) {
       const uint64_t next = tile + gridDim.x;
       const bool more = next < g.ntiles;
-      if (more) pass_dma_tile<PITERS, PT>(rho, pass_tile_base(g, next), off, (t & 1) ? ldsA : ldsB, wave);
+      if (more) {
+        // tbase[(t + 1) & 1] was last read before this tile's B0
+        const uint64_t base = pass_tile_base(g, next);
+        if (tid == 0) tbase[(t + 1) & 1] = base;
+        pass_dma_tile<T, PITERS, PT>(rho, base, off, (t & 1) ? ldsA : ldsB, wave);
+      }
       for (int j = 0; j <= g.m; ++j) raw_barrier();  // the m superoperators, then B_free
       if (!more) break;
       vm_wait<0>();
@@ -303,15 +206,15 @@ __global__ __launch_bounds__(NT) void apply_pass_ws_kernel(double* __restrict__ 
     const int ct = tid - PT;    // consumer thread 0..CT-1
     uint64_t off[CITERS];
 #pragma unroll
-    for (int it = 0; it < CITERS; ++it) off[it] = pass_slot_off<VMAX>((uint32_t)(it * CT + ct), g);
+    for (int it = 0; it < CITERS; ++it) off[it] = pass_slot_off<T, VMAX>((uint32_t)((it * CT + ct) * EPS), g);
     raw_barrier();  // B0: first tile ready
     for (int t = 0;; ++t) {
-      const uint64_t cur = pass_tile_base(g, tile);
+      const uint64_t cur = tbase[t & 1];
       const uint64_t next = tile + gridDim.x;
       const bool more = next < g.ntiles;
       u32x4* buf = (t & 1) ? ldsB : ldsA;
       for (int j = 0; j < g.m; ++j) {
-        pass_superop_f64<VMAX, NCW>(reinterpret_cast<double*>(buf), opl, gxt, g, j, cw, lane);
+        pass_superop<T, VMAX, NCW>(reinterpret_cast<T*>(buf), opl, gxt, g, j, cw, lane);
         raw_barrier();  // the next superoperator (or the store) reads what other waves wrote
       }
 #pragma unroll
@@ -324,17 +227,17 @@ __global__ __launch_bounds__(NT) void apply_pass_ws_kernel(double* __restrict__ 
   }
 }
 
-// Tile shapes: 2^12 FP64 elements (64 KiB, six qubits) with 512 threads; 2^13 FP32 elements
-// (64 KiB, six qubits and one more bit) with 512 threads.
+// Tile sizes: 2^12 FP64 elements or 2^13 FP32 elements (64 KiB: six qubits, and one more bit
+// in FP32).
 template <typename T>
 struct PassShape;
 template <>
-struct PassShape<double> { static constexpr int V = 12, NT = 512; };
+struct PassShape<double> { static constexpr int V = 12; };
 template <>
-struct PassShape<float> { static constexpr int V = 13, NT = 512; };
+struct PassShape<float> { static constexpr int V = 13; };
 
 int pass_tile_bits(tanq_prec p) { return p == TANQ_F64 ? PassShape<double>::V : PassShape<float>::V; }
-int pass_max(tanq_prec p) { return p == TANQ_F64 ? kPassWsMax : kPassMax; }
+int pass_max(tanq_prec p) { return p == TANQ_F64 ? PassWsMax<double>::M : PassWsMax<float>::M; }
 
 static std::atomic<int> g_pass_limit{kPassMax};
 int pass_limit() { return g_pass_limit.load(); }
@@ -401,8 +304,8 @@ int swz_score(const SwzProblem& P, const uint8_t* xcol) {
 }
 
 // Upper bound of swz_score over all swizzles: a pattern's vectors from bits inside the window
-// are fixed unit vectors; those from bits above it can be any vectors, so a pattern can reach
-// full rank only if its fixed vectors are distinct.
+// are fixed unit vectors; those from bits above it can be any vectors of the allowed columns
+// (FP32 columns never set bit 0, so an FP32 pattern spans bit 0 only through tile bit 0).
 int swz_bound(const SwzProblem& P) {
   auto ok = [&](const uint32_t* bits, int cnt) {
     uint32_t fixed = 0;
@@ -415,6 +318,7 @@ int swz_bound(const SwzProblem& P) {
         ++above;
       }
     }
+    if (P.W == 5) return (fixed & 1u) && above <= 4 - __builtin_popcount(fixed & ~1u);
     return above <= P.W - __builtin_popcount(fixed);
   };
   int b = 0;
@@ -442,7 +346,8 @@ uint64_t splitmix(uint64_t& s) {
 
 }  // namespace
 
-PassGeom make_pass_geom(int n, int m, const int* qubits, const uint32_t* op_off, tanq_prec p, int* conflict_free) {
+PassGeom make_pass_geom(int n, int m, const int* qubits, const uint32_t* op_off, tanq_prec p, int* conflict_free,
+                        int* achievable) {
   if (m < 1 || m > kPassMax) fail(TANQ_E_ARG, "pass length outside 1..kPassMax");
   PassGeom g;
   std::memset(&g, 0, sizeof(g));
@@ -512,7 +417,9 @@ PassGeom make_pass_geom(int n, int m, const int* qubits, const uint32_t* op_off,
   int best_score = swz_score(P, best);
   const int perfect = swz_bound(P);
   uint64_t seed = 0x7A3Cull ^ ((uint64_t)n << 32) ^ (uint64_t)m;
-  const uint32_t wmask = (1u << P.W) - 1u;
+  // FP32 columns never set bit 0: a 16-byte slot's two elements keep their order, as the
+  // global-to-LDS loads require
+  const uint32_t wmask = ((1u << P.W) - 1u) & (p == TANQ_F64 ? ~0u : ~1u);
   for (int trial = 0; trial < 4000 && best_score < perfect; ++trial) {
     uint8_t cand[16] = {0};
     const uint64_t r0 = splitmix(seed), r1 = splitmix(seed);
@@ -528,6 +435,7 @@ PassGeom make_pass_geom(int n, int m, const int* qubits, const uint32_t* op_off,
   }
   std::memcpy(g.xcol, best, sizeof(best));
   if (conflict_free) *conflict_free = best_score;
+  if (achievable) *achievable = perfect;
   auto S = [&](uint32_t e) {
     uint32_t x = e;
     for (int b = P.W; b < 16; ++b)
@@ -536,10 +444,10 @@ PassGeom make_pass_geom(int n, int m, const int* qubits, const uint32_t* op_off,
   };
   for (int j = 0; j < m; ++j)
     for (int l = 0; l < 16; ++l) g.stj[j][l] = S(tj[j][l]);
-  // the swizzle is an involution of [0, 2^V) that keeps FP32 slot pairs in one slot
+  // the swizzle is an involution of [0, 2^V) that keeps FP32 slot pairs whole and in order
   for (uint32_t e = 0; e < (1u << V); ++e) {
     const uint32_t s = S(e);
-    if (s >= (1u << V) || S(s) != e || (S(e ^ 1u) != (s ^ 1u)))
+    if (s >= (1u << V) || S(s) != e || (p != TANQ_F64 && ((s ^ e) & 1u)))
       fail(TANQ_E_STATE, "pass swizzle is not an involution");
   }
 
@@ -565,11 +473,13 @@ PassGeom make_pass_geom(int n, int m, const int* qubits, const uint32_t* op_off,
   return g;
 }
 
+// Specialised-wave shape: 640 threads, 2 producer and 8 consumer waves.
 template <typename T>
-static void launch_pass_typed(void* rho, const PassGeom& g, const void* frags, hipStream_t s) {
-  constexpr int V = PassShape<T>::V, NT = PassShape<T>::NT;
+static void launch_pass_ws(void* rho, const PassGeom& g, const void* frags, hipStream_t s) {
+  constexpr int V = PassShape<T>::V, NT = 640, NPW = 2;
   if (g.V != V) fail(TANQ_E_STATE, "pass geometry built for another tile size");
-  auto kern = apply_pass_kernel<T, V, NT>;
+  if (g.m < 1 || g.m > PassWsMax<T>::M) fail(TANQ_E_STATE, "pass longer than its operand buffers");
+  auto kern = apply_pass_ws_kernel<T, V, NT, NPW>;
   static thread_local int cap_dev = -1;
   static thread_local uint64_t cap = 0;
   int dev = 0;
@@ -585,33 +495,11 @@ static void launch_pass_typed(void* rho, const PassGeom& g, const void* frags, h
   TANQ_HIP(hipGetLastError());
 }
 
-// FP64 wave-specialised shape: 640 threads, 2 producer and 8 consumer waves.
-
-template <int V, int NT, int NPW>
-static void launch_pass_ws(void* rho, const PassGeom& g, const void* frags, hipStream_t s) {
-  if (g.V != V) fail(TANQ_E_STATE, "pass geometry built for another tile size");
-  if (g.m < 1 || g.m > kPassWsMax) fail(TANQ_E_STATE, "FP64 pass longer than its operand buffers");
-  auto kern = apply_pass_ws_kernel<V, NT, NPW>;
-  static thread_local int cap_dev = -1;
-  static thread_local uint64_t cap = 0;
-  int dev = 0;
-  TANQ_HIP(hipGetDevice(&dev));
-  if (cap_dev != dev) {
-    int per_cu = 0;
-    TANQ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, NT, 0));
-    cap = (uint64_t)device_cu_count() * (uint64_t)(per_cu < 1 ? 1 : per_cu);
-    cap_dev = dev;
-  }
-  const uint64_t grid = g.ntiles < cap ? g.ntiles : cap;
-  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(NT), 0, s, (double*)rho, (const double*)frags, g);
-  TANQ_HIP(hipGetLastError());
-}
-
 void launch_pass(void* rho, tanq_prec p, const PassGeom& g, const void* frags, hipStream_t s) {
   if (p == TANQ_F64)
-    launch_pass_ws<PassShape<double>::V, 640, 2>(rho, g, frags, s);
+    launch_pass_ws<double>(rho, g, frags, s);
   else
-    launch_pass_typed<float>(rho, g, frags, s);
+    launch_pass_ws<float>(rho, g, frags, s);
 }
 
 }  // namespace tanq

@@ -139,7 +139,7 @@ _SIGS = {
     "tanq_autotune_dense": ([_vp, ctypes.c_int, _dp], ctypes.c_int),
     "tanq_set_pass_limit": ([ctypes.c_int], ctypes.c_int),
     "tanq_get_pass_limit": ([_ip], ctypes.c_int),
-    "tanq_pass_layout_info": ([ctypes.c_int, ctypes.c_int, _ip, ctypes.c_int, _ip], ctypes.c_int),
+    "tanq_pass_layout_info": ([ctypes.c_int, ctypes.c_int, _ip, ctypes.c_int, _ip, _ip], ctypes.c_int),
     "tanq_fused_passes": ([_vp, _ip, _ip], ctypes.c_int),
     "tanq_fused_launches": ([_vp, _ip, ctypes.c_int, _ip], ctypes.c_int),
     "tanq_tuning_export": ([ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
@@ -432,12 +432,13 @@ def tanq_fused_launches(h: int) -> List[int]:
     return list(buf[:cnt.value])
 
 
-def tanq_pass_layout_info(n: int, pairs: Sequence[Sequence[int]], prec) -> int:
-    """Conflict-free LDS access patterns (of 2 per superoperator) of one pass layout."""
+def tanq_pass_layout_info(n: int, pairs: Sequence[Sequence[int]], prec):
+    """(conflict-free LDS access patterns, their achievable maximum) of one pass layout; two
+    patterns per superoperator."""
     flat = [int(q) for pr in pairs for q in pr]
-    v = ctypes.c_int()
-    _check(load().tanq_pass_layout_info(n, len(pairs), _ints(flat), _prec(prec), ctypes.byref(v)))
-    return v.value
+    v, b = ctypes.c_int(), ctypes.c_int()
+    _check(load().tanq_pass_layout_info(n, len(pairs), _ints(flat), _prec(prec), ctypes.byref(v), ctypes.byref(b)))
+    return v.value, b.value
 
 
 def tanq_tuning_export() -> str:
