@@ -223,6 +223,50 @@ int pass_run(BlockAt at, int i, int end, int n, tanq_prec p, int lim) {
   return m;
 }
 
+// Reorder a block list so that 2-qubit blocks that can share a pass are adjacent.  From the
+// first block not yet placed, later 2-qubit blocks (within a short window) join its pass while
+// they fit the pass tile, provided they commute with every block they move ahead of (disjoint
+// qubits); a block that does not join keeps its place and blocks its qubits for the rest of the
+// scan.  Reordering commuting superoperators leaves the product unchanged.  Returns the list
+// unchanged where passes do not apply.
+std::vector<PlanBlock> pass_order(const std::vector<PlanBlock>& pl, int n, tanq_prec p, int lim) {
+  const int V = pass_tile_bits(p);
+  const int min_run = p == TANQ_F64 ? 3 : 4;
+  constexpr size_t kWindow = 16;
+  lim = std::min(lim, pass_max(p));
+  if (lim < 2 || 2 * n - V < kPassMinTileBits) return pl;
+  auto qmask = [&](int b) {
+    uint64_t m = 0;
+    for (int q : pl[b].qubits) m |= 1ull << q;
+    return m;
+  };
+  std::vector<int> rem(pl.size());
+  for (size_t i = 0; i < rem.size(); ++i) rem[i] = (int)i;
+  std::vector<PlanBlock> out;
+  out.reserve(pl.size());
+  std::vector<size_t> take;
+  while (!rem.empty()) {
+    take.assign(1, 0);
+    const int b0 = rem[0];
+    if (pl[b0].qubits.size() == 2) {
+      uint64_t U = qmask(b0), blocked = 0;
+      for (size_t pos = 1; pos < rem.size() && pos < kWindow && (int)take.size() < lim; ++pos) {
+        const int b = rem[pos];
+        const uint64_t qb = qmask(b);
+        if (pl[b].qubits.size() == 2 && !(qb & blocked) && pass_low_run(U | qb, n, V) >= min_run) {
+          take.push_back(pos);
+          U |= qb;
+        } else {
+          blocked |= qb;
+        }
+      }
+    }
+    for (size_t t : take) out.push_back(pl[rem[t]]);
+    for (auto it = take.rbegin(); it != take.rend(); ++it) rem.erase(rem.begin() + (ptrdiff_t)*it);
+  }
+  return out;
+}
+
 extern "C" {
 
 const char* tanq_last_error(void) { return g_last_error.c_str(); }
@@ -522,7 +566,7 @@ tanq_status tanq_fuse(tanq_circuit c, int max_width, tanq_prec p, void* hip_stre
     if (mode == TANQ_FUSE_AUTO) {
       double best = 1e300;
       for (int w = 2; w <= std::min(3, n); ++w) {
-        std::vector<PlanBlock> pl = plan_fusion(pops, n, w);
+        std::vector<PlanBlock> pl = pass_order(plan_fusion(pops, n, w), n, p, pass_limit());
         const double cost = plan_cost(pl, n, p);
         if (cost < best) {
           best = cost;
@@ -535,7 +579,7 @@ tanq_status tanq_fuse(tanq_circuit c, int max_width, tanq_prec p, void* hip_stre
         mode = 1;
       }
     } else {
-      plan = plan_fusion(pops, n, mode);
+      plan = pass_order(plan_fusion(pops, n, mode), n, p, pass_limit());
     }
 
     std::unique_ptr<tanq_fused_s> f(new tanq_fused_s);

@@ -1,8 +1,8 @@
 """Multi-superoperator passes: runs of 2-qubit blocks applied in one pass over vec(rho).
 
 Each pass performs, per superoperator, the same per-group MFMA sequence as a single apply, so
-the state after tanq_apply_fused with passes must equal, bit for bit, the state with passes
-switched off (limit 1); FP64 must also match the CPU oracle within 1e-10.  Sizes: the smallest
+the state after tanq_apply_fused with passes must equal, bit for bit, the state of the same
+fused list applied with passes switched off (limit 1); FP64 must also match the CPU oracle within 1e-10.  Sizes: the smallest
 states that use passes (n = 10 in FP64, n = 11 in FP32: at least 256 pass tiles) and a
 12-qubit state, compared on every element.  Circuits: the random U3/CX circuit (random pairs, so passes mix
 low and high qubits) and the nearest-neighbour brickwork (passes on neighbouring qubits, low
@@ -23,12 +23,15 @@ def say(*a):
     sys.stdout.flush()
 
 
-def run_fused(n, ops, prec, limit, rho_in=None):
+def run_fused(n, ops, prec, limit, rho_in=None, fuse_limit=8):
+    """Fuse at width 2 under pass limit fuse_limit (which orders the blocks for passes), then
+    apply under pass limit `limit` (1 = every block on its own)."""
     old = T.tanq_get_pass_limit()
-    T.tanq_set_pass_limit(limit)
     try:
+        T.tanq_set_pass_limit(fuse_limit)
         c = T.Circuit(n, ops)
         f = c.fuse(2, prec)
+        T.tanq_set_pass_limit(limit)
         passes = f.passes()
         d = T.DM(n, prec)
         if rho_in is not None:
@@ -121,6 +124,7 @@ def test_launch_ranges_reproduce_apply_fused():
         runs = f.launches()
         np_, nin = f.passes()
         assert sum(runs) == f.count and np_ > 0
+        assert max(runs) >= 3  # blocks reordered by qubit set make passes of three
         assert sum(1 for r in runs if r >= 2) == np_ and sum(r for r in runs if r >= 2) == nin
         d1, d2 = T.DM(n, prec), T.DM(n, prec)
         d1.apply_fused(f)
