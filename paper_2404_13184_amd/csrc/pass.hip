@@ -98,31 +98,41 @@ __device__ inline void pass_superop(T* ldsT, const T (*opl)[1024], const uint16_
     for (int s = 0; s < KS; ++s) afr[m][s] = opl[j][(m * KS + s) * 64 + lane];
   const uint32_t* st = g.stj[j];
   const uint32_t s1 = hb ? st[1] : 0u;
+  // the wave's column blocks are multiplied together, k-step by k-step, so that 2 x NBW
+  // independent accumulation chains keep the matrix pipe busy
+  uint32_t gx[NBW];
+  acc_t acc[NBW][MT];
 #pragma unroll
   for (int i = 0; i < NBW; ++i) {
-    const uint32_t gx = gxt[j][(cw + i * NCW) * 16 + (lane & 15)];
-    acc_t acc[MT];
+    gx[i] = gxt[j][(cw + i * NCW) * 16 + (lane & 15)];
 #pragma unroll
-    for (int m = 0; m < MT; ++m) acc[m] = acc_t{0, 0, 0, 0};
+    for (int m = 0; m < MT; ++m) acc[i][m] = acc_t{0, 0, 0, 0};
+  }
 #pragma unroll
-    for (int s = 0; s < KS; ++s) {
-      const T bv = ldsT[2 * ((st[2 * s] ^ s1) ^ gx) + cc];
+  for (int s = 0; s < KS; ++s) {
+    T bv[NBW];
 #pragma unroll
-      for (int m = 0; m < MT; ++m) acc[m] = M::mma(afr[m][s], bv, acc[m]);
-    }
-    // a wave writes only the groups it read, so no barrier inside one superoperator
+    for (int i = 0; i < NBW; ++i) bv[i] = ldsT[2 * ((st[2 * s] ^ s1) ^ gx[i]) + cc];
+#pragma unroll
+    for (int i = 0; i < NBW; ++i)
+#pragma unroll
+      for (int m = 0; m < MT; ++m) acc[i][m] = M::mma(afr[m][s], bv[i], acc[i][m]);
+  }
+  // a wave writes only the groups it read, so no barrier inside one superoperator
+#pragma unroll
+  for (int i = 0; i < NBW; ++i) {
 #pragma unroll
     for (int m = 0; m < MT; ++m) {
       if constexpr (M::kRowsStrided) {
         // value r = real row kk + 4r of m-tile m: component cc of output a = 8m + 2r + hb
 #pragma unroll
-        for (int r = 0; r < 4; ++r) ldsT[2 * ((st[8 * m] ^ st[2 * r] ^ s1) ^ gx) + cc] = acc[m][r];
+        for (int r = 0; r < 4; ++r) ldsT[2 * ((st[8 * m] ^ st[2 * r] ^ s1) ^ gx[i]) + cc] = acc[i][m][r];
       } else {
         // values (0,1), (2,3) = (re, im) of outputs a = 8m + 2kk and a + 1
         const uint32_t tq = ((kk & 1) ? st[2] : 0u) ^ ((kk & 2) ? st[4] : 0u);
-        const uint32_t e0 = (st[8 * m] ^ tq) ^ gx;
-        *reinterpret_cast<c2*>(ldsT + 2 * e0) = c2{acc[m][0], acc[m][1]};
-        *reinterpret_cast<c2*>(ldsT + 2 * (e0 ^ st[1])) = c2{acc[m][2], acc[m][3]};
+        const uint32_t e0 = (st[8 * m] ^ tq) ^ gx[i];
+        *reinterpret_cast<c2*>(ldsT + 2 * e0) = c2{acc[i][m][0], acc[i][m][1]};
+        *reinterpret_cast<c2*>(ldsT + 2 * (e0 ^ st[1])) = c2{acc[i][m][2], acc[i][m][3]};
       }
     }
   }
