@@ -223,12 +223,14 @@ int pass_run(BlockAt at, int i, int end, int n, tanq_prec p, int lim) {
   return m;
 }
 
-// Reorder a block list so that 2-qubit blocks that can share a pass are adjacent.  From the
-// first block not yet placed, later 2-qubit blocks (within a short window) join its pass while
+// Reorder a block list so that blocks that can share a pass are adjacent.  From the first
+// block not yet placed, later 1- and 2-qubit blocks (within a short window) join its pass while
 // they fit the pass tile, provided they commute with every block they move ahead of (disjoint
 // qubits); a block that does not join keeps its place and blocks its qubits for the rest of the
-// scan.  Reordering commuting superoperators leaves the product unchanged.  Returns the list
-// unchanged where passes do not apply.
+// scan.  One-qubit members of a pass are widened to two qubits (the identity on a qubit the
+// pass already holds), since a pass applies 2-qubit superoperators.  Reordering commuting
+// superoperators leaves the product unchanged.  Returns the list unchanged where passes do
+// not apply.
 std::vector<PlanBlock> pass_order(const std::vector<PlanBlock>& pl, int n, tanq_prec p, int lim) {
   const int V = pass_tile_bits(p);
   const int min_run = p == TANQ_F64 ? 3 : 4;
@@ -248,12 +250,13 @@ std::vector<PlanBlock> pass_order(const std::vector<PlanBlock>& pl, int n, tanq_
   while (!rem.empty()) {
     take.assign(1, 0);
     const int b0 = rem[0];
-    if (pl[b0].qubits.size() == 2) {
-      uint64_t U = qmask(b0), blocked = 0;
+    uint64_t U = qmask(b0);
+    if (pl[b0].qubits.size() <= 2) {
+      uint64_t blocked = 0;
       for (size_t pos = 1; pos < rem.size() && pos < kWindow && (int)take.size() < lim; ++pos) {
         const int b = rem[pos];
         const uint64_t qb = qmask(b);
-        if (pl[b].qubits.size() == 2 && !(qb & blocked) && pass_low_run(U | qb, n, V) >= min_run) {
+        if (pl[b].qubits.size() <= 2 && !(qb & blocked) && pass_low_run(U | qb, n, V) >= min_run) {
           take.push_back(pos);
           U |= qb;
         } else {
@@ -261,7 +264,17 @@ std::vector<PlanBlock> pass_order(const std::vector<PlanBlock>& pl, int n, tanq_
         }
       }
     }
-    for (size_t t : take) out.push_back(pl[rem[t]]);
+    const bool pass = take.size() >= 2 && __builtin_popcountll(U) >= 2;
+    for (size_t t : take) {
+      PlanBlock b = pl[rem[t]];
+      if (pass && b.qubits.size() == 1) {
+        const int q = b.qubits[0];
+        const uint64_t others = U & ~(1ull << q);
+        b.qubits.push_back(__builtin_ctzll(others));
+        std::sort(b.qubits.begin(), b.qubits.end());
+      }
+      out.push_back(std::move(b));
+    }
     for (auto it = take.rbegin(); it != take.rend(); ++it) rem.erase(rem.begin() + (ptrdiff_t)*it);
   }
   return out;
