@@ -51,7 +51,7 @@ __device__ inline uint32_t pass_swz(uint32_t e, const PassGeom& g) {
 __device__ inline uint64_t pass_tile_base(const PassGeom& g, uint64_t tile) {
   uint64_t b = 0;
 #pragma unroll
-  for (int r = 0; r < 16; ++r)  // constant indices keep the run table in scalar registers
+  for (int r = 0; r < 16; ++r)  // constant indices into the kernel-argument run table
     if (r < g.nruns) b |= ((tile >> g.run_src[r]) & ((1ull << g.run_len[r]) - 1ull)) << g.run_dst[r];
   return b;
 }
