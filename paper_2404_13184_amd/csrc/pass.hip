@@ -78,64 +78,79 @@ __device__ inline uint64_t pass_slot_off(uint32_t first, const PassGeom& g) {
   return o;
 }
 
-// One superoperator of a pass on the tile in ldsT, by consumer wave cw of NCW: the same
-// real-block MFMA sequence as the single apply (Op2), with the pass's swizzled offsets.
+// Operands of a pass in LDS: each 2-qubit superoperator in 3M form, Sr, Si and Sr + Si as
+// 4 k-steps x 3 x 64 lane fragments (lane l holds row l % 16, column 4 s + l / 16).
+constexpr int kOp3M = 4 * 3 * 64;
+
+// Build the 3M fragments of superoperator j from its real-block packing (the single-apply
+// operand: the 32 x 32 real matrix [[Sr, -Si], [Si, Sr]] on interleaved indices, in MFMA lane
+// order: element (R, C) at ((R / 16) * 8 + C / 4) * 64 + (C % 4) * 16 + R % 16).
+template <typename T>
+__device__ inline T pass_op3m(const T* __restrict__ rb, int r) {
+  const int s3 = r / 192, t = (r / 64) % 3, lane = r % 64;
+  const int a = lane % 16, b = 4 * s3 + lane / 16;  // complex row and column
+  auto at = [&](int R, int C) { return rb[((R / 16) * 8 + C / 4) * 64 + (C % 4) * 16 + R % 16]; };
+  const T sr = at(2 * a, 2 * b), si = at(2 * a + 1, 2 * b);
+  return t == 0 ? sr : (t == 1 ? si : sr + si);
+}
+
+// One superoperator of a pass on the tile in ldsC, by consumer wave cw of NCW, in 3M form:
+// P1 = Sr xr, P2 = Si xi, P3 = (Sr + Si)(xr + xi); Re = P1 - P2, Im = P3 - P1 - P2 -- three
+// real 16 x 16 products per group instead of the real-block form's four.  A wave multiplies its
+// column blocks together, k-step by k-step (independent accumulation chains), and writes only
+// the groups it read, so no barrier inside one superoperator.
 template <typename T, int VMAX, int NCW>
-__device__ inline void pass_superop(T* ldsT, const T (*opl)[1024], const uint16_t (*gxt)[1 << (VMAX - 4)],
-                                    const PassGeom& g, int j, int cw, int lane) {
+__device__ inline void pass_superop(typename Mfma<T>::c2* ldsC, const T (*opl)[kOp3M],
+                                    const uint16_t (*gxt)[1 << (VMAX - 4)], const PassGeom& g, int j, int cw,
+                                    int lane) {
   using M = Mfma<T>;
   using acc_t = typename M::acc_t;
   using c2 = typename M::c2;
   constexpr int NB = (1 << (VMAX - 4)) / 16;
   constexpr int NBW = NB / NCW;
   static_assert(NB % NCW == 0, "every consumer wave gets the same number of column blocks");
-  constexpr int MT = 2, KS = 8;
-  const int kk = lane >> 4, cc = kk & 1, hb = kk >> 1;
-  T afr[MT][KS];
+  constexpr int KS = 4;
+  const int kk = lane >> 4;
+  T ar[KS], ai[KS], as[KS];
 #pragma unroll
-  for (int m = 0; m < MT; ++m)
-#pragma unroll
-    for (int s = 0; s < KS; ++s) afr[m][s] = opl[j][(m * KS + s) * 64 + lane];
+  for (int s = 0; s < KS; ++s) {
+    ar[s] = opl[j][(s * 3 + 0) * 64 + lane];
+    ai[s] = opl[j][(s * 3 + 1) * 64 + lane];
+    as[s] = opl[j][(s * 3 + 2) * 64 + lane];
+  }
   const uint32_t* st = g.stj[j];
-  const uint32_t s1 = hb ? st[1] : 0u;
-  // the wave's column blocks are multiplied together, k-step by k-step, so that 2 x NBW
-  // independent accumulation chains keep the matrix pipe busy
+  const uint32_t skk = ((kk & 1) ? st[1] : 0u) ^ ((kk & 2) ? st[2] : 0u);  // S(tile index of row kk)
   uint32_t gx[NBW];
-  acc_t acc[NBW][MT];
+  acc_t p1[NBW], p2[NBW], p3[NBW];
 #pragma unroll
   for (int i = 0; i < NBW; ++i) {
     gx[i] = gxt[j][(cw + i * NCW) * 16 + (lane & 15)];
-#pragma unroll
-    for (int m = 0; m < MT; ++m) acc[i][m] = acc_t{0, 0, 0, 0};
+    p1[i] = acc_t{0, 0, 0, 0};
+    p2[i] = acc_t{0, 0, 0, 0};
+    p3[i] = acc_t{0, 0, 0, 0};
   }
 #pragma unroll
   for (int s = 0; s < KS; ++s) {
-    T bv[NBW];
+    c2 v[NBW];
 #pragma unroll
-    for (int i = 0; i < NBW; ++i) bv[i] = ldsT[2 * ((st[2 * s] ^ s1) ^ gx[i]) + cc];
+    for (int i = 0; i < NBW; ++i) v[i] = ldsC[(st[4 * s] ^ skk) ^ gx[i]];
 #pragma unroll
-    for (int i = 0; i < NBW; ++i)
-#pragma unroll
-      for (int m = 0; m < MT; ++m) acc[i][m] = M::mma(afr[m][s], bv[i], acc[i][m]);
-  }
-  // a wave writes only the groups it read, so no barrier inside one superoperator
-#pragma unroll
-  for (int i = 0; i < NBW; ++i) {
-#pragma unroll
-    for (int m = 0; m < MT; ++m) {
-      if constexpr (M::kRowsStrided) {
-        // value r = real row kk + 4r of m-tile m: component cc of output a = 8m + 2r + hb
-#pragma unroll
-        for (int r = 0; r < 4; ++r) ldsT[2 * ((st[8 * m] ^ st[2 * r] ^ s1) ^ gx[i]) + cc] = acc[i][m][r];
-      } else {
-        // values (0,1), (2,3) = (re, im) of outputs a = 8m + 2kk and a + 1
-        const uint32_t tq = ((kk & 1) ? st[2] : 0u) ^ ((kk & 2) ? st[4] : 0u);
-        const uint32_t e0 = (st[8 * m] ^ tq) ^ gx[i];
-        *reinterpret_cast<c2*>(ldsT + 2 * e0) = c2{acc[i][m][0], acc[i][m][1]};
-        *reinterpret_cast<c2*>(ldsT + 2 * (e0 ^ st[1])) = c2{acc[i][m][2], acc[i][m][3]};
-      }
+    for (int i = 0; i < NBW; ++i) {
+      const T br = v[i][0], bi = v[i][1];
+      p1[i] = M::mma(ar[s], br, p1[i]);
+      p2[i] = M::mma(ai[s], bi, p2[i]);
+      p3[i] = M::mma(as[s], br + bi, p3[i]);
     }
   }
+  // output row of accumulator value r: kk + 4 r (FP64) or 4 kk + r (FP32)
+  const uint32_t srow = M::kRowsStrided ? skk : (((kk & 1) ? st[4] : 0u) ^ ((kk & 2) ? st[8] : 0u));
+#pragma unroll
+  for (int i = 0; i < NBW; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const uint32_t e = (srow ^ (M::kRowsStrided ? st[4 * r] : st[r])) ^ gx[i];
+      ldsC[e] = c2{p1[i][r] - p2[i][r], p3[i][r] - p1[i][r] - p2[i][r]};
+    }
 }
 
 // Producer: stream one tile into buf with direct global-to-LDS loads (lane data lands at the
@@ -163,7 +178,7 @@ __global__ __launch_bounds__(NT) void apply_pass_ws_kernel(T* __restrict__ rho, 
 
   __shared__ u32x4 ldsA[SLOTS];
   __shared__ u32x4 ldsB[SLOTS];
-  __shared__ T opl[MMAX][1024];
+  __shared__ T opl[MMAX][kOp3M];
   __shared__ uint16_t gxt[MMAX][G];
   // base offset of the tile in each buffer, written by the producer with its loads: the
   // consumers take it from LDS rather than recomputing it from the run table (which the
@@ -176,7 +191,8 @@ __global__ __launch_bounds__(NT) void apply_pass_ws_kernel(T* __restrict__ rho, 
 
   uint64_t tile = xcd_first_tile();
   if (tile >= g.ntiles) return;  // uniform per workgroup
-  for (int idx = tid; idx < g.m * 1024; idx += NT) opl[idx >> 10][idx & 1023] = frags[g.op_off[idx >> 10] + (idx & 1023)];
+  for (int idx = tid; idx < g.m * kOp3M; idx += NT)
+    opl[idx / kOp3M][idx % kOp3M] = pass_op3m<T>(frags + g.op_off[idx / kOp3M], idx % kOp3M);
   for (int idx = tid; idx < g.m * G; idx += NT) {
     const int j = idx / G, gi = idx % G;
     gxt[j][gi] = (uint16_t)pass_swz<T>(pdep32((uint32_t)gi, g.free_mask[j]), g);
@@ -224,7 +240,7 @@ __global__ __launch_bounds__(NT) void apply_pass_ws_kernel(T* __restrict__ rho, 
       const bool more = next < g.ntiles;
       u32x4* buf = (t & 1) ? ldsB : ldsA;
       for (int j = 0; j < g.m; ++j) {
-        pass_superop<T, VMAX, NCW>(reinterpret_cast<T*>(buf), opl, gxt, g, j, cw, lane);
+        pass_superop<T, VMAX, NCW>(reinterpret_cast<typename Mfma<T>::c2*>(buf), opl, gxt, g, j, cw, lane);
         raw_barrier();  // the next superoperator (or the store) reads what other waves wrote
       }
 #pragma unroll
@@ -417,8 +433,8 @@ PassGeom make_pass_geom(int n, int m, const int* qubits, const uint32_t* op_off,
     int q = 0;
     for (int b = 0; b < V && q < 4; ++b)
       if ((g.free_mask[j] >> b) & 1u) P.fbits[j][q++] = (uint32_t)b;
-    P.t1[j] = tj[j][1];
-    P.t2[j] = tj[j][2];
+    P.t1[j] = tj[j][1];  // FP32 operand reads: lanes 0-31 cover rows 0 and 1
+    P.t2[j] = tj[j][4];  // FP32 result writes: lanes 0-31 cover rows 0-3 and 4-7
   }
 
   // swizzle: the identity first, then seeded random candidates, keeping the best (reaching the

@@ -1,8 +1,9 @@
 """Multi-superoperator passes: runs of 2-qubit blocks applied in one pass over vec(rho).
 
-Each pass performs, per superoperator, the same per-group MFMA sequence as a single apply, so
-the state after tanq_apply_fused with passes must equal, bit for bit, the state of the same
-fused list applied with passes switched off (limit 1); FP64 must also match the CPU oracle within 1e-10.  Sizes: the smallest
+A pass multiplies each superoperator in 3M form (three real products) where a single apply
+uses the real-block form, so the state after tanq_apply_fused with passes must match the state
+of the same fused list applied with passes switched off (limit 1) to rounding (relative 1e-12
+in FP64, 1e-5 in FP32); FP64 must also match the CPU oracle within 1e-10.  Sizes: the smallest
 states that use passes (n = 10 in FP64, n = 11 in FP32: at least 256 pass tiles) and a
 12-qubit state, compared on every element.  Circuits: the random U3/CX circuit (random pairs, so passes mix
 low and high qubits) and the nearest-neighbour brickwork (passes on neighbouring qubits, low
@@ -51,15 +52,22 @@ def circuits(n):
             ("brick", W.brickwork_cz(n, 6, 7 + n, 1e-3, 1e-2, 1e-3))]
 
 
+TOL = {"f64": 1e-12, "f32": 1e-5}
+
+
+def close(got, want, prec):
+    return np.abs(got - want).max() <= TOL[prec] * np.abs(want).max()
+
+
 @pytest.mark.parametrize("prec,n", [("f64", 10), ("f64", 11), ("f32", 11)])
-def test_passes_bitwise_equal_to_single_applies(prec, n):
+def test_passes_match_single_applies(prec, n):
     for name, ops in circuits(n):
         say("passes %s n=%d %s" % (prec, n, name))
         want, p0 = run_fused(n, ops, prec, 1)
         got, p1 = run_fused(n, ops, prec, 8)
         assert p0 == (0, 0)
         assert p1[0] > 0 and p1[1] >= 2 * p1[0]  # passes were used
-        assert np.array_equal(got.view(np.uint8), want.view(np.uint8))
+        assert close(got, want, prec)
 
 
 @pytest.mark.parametrize("limit", [2, 3, 5])
@@ -70,7 +78,7 @@ def test_pass_limits(limit):
     want, _ = run_fused(n, ops, "f64", 1)
     got, (np_, nin) = run_fused(n, ops, "f64", limit)
     assert np_ > 0 and nin <= limit * np_
-    assert np.array_equal(got.view(np.uint8), want.view(np.uint8))
+    assert close(got, want, "f64")
 
 
 def test_passes_match_oracle_f64(oracle_mod):
@@ -102,14 +110,14 @@ def test_passes_on_a_dense_input_f32(oracle_mod):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_passes_bitwise_12_qubits(prec):
+def test_passes_12_qubits(prec):
     n = 12
     ops = W.random_u3_cx(n, 3, 12, 1e-3, 1e-2, gamma=5e-4)
     say("passes %s n=%d full compare" % (prec, n))
     want, _ = run_fused(n, ops, prec, 1)
     got, (np_, _) = run_fused(n, ops, prec, 8)
     assert np_ > 0
-    assert np.array_equal(got.view(np.uint8), want.view(np.uint8))
+    assert close(got, want, prec)
 
 
 def test_launch_ranges_reproduce_apply_fused():
