@@ -238,7 +238,7 @@ tanq_status tanq_autotune_dense(tanq_dm d, int reps, double* ms_per_apply);
  * those of applying the blocks one by one), and written back once.  This cuts HBM traffic, the
  * bound of 2-qubit applies (Sec. 3.2: a 2-qubit superoperator is memory-bound).  Passes are
  * used on states of at least 10 (FP64) or 11 (FP32) qubits, for runs whose tiles keep whole
- * 128-byte lines of vec(rho), with at most 3 (FP64) or 4 (FP32) superoperators.  With passes
+ * 128-byte lines of vec(rho), with at most 4 (FP64) or 6 (FP32) superoperators.  With passes
  * enabled, tanq_fuse also orders commuting blocks so that blocks sharing a pass are adjacent,
  * and widens 1-qubit blocks that join a pass to 2 qubits (the identity on the added qubit).  The limit is
  * the most superoperators per pass, 1..8 (1 = no passes; default 8), process-wide. */

@@ -63,9 +63,9 @@ __device__ inline uint64_t pass_tile_base(const PassGeom& g, uint64_t tile) {
 template <typename T>
 struct PassWsMax;
 template <>
-struct PassWsMax<double> { static constexpr int M = 3; };
+struct PassWsMax<double> { static constexpr int M = 4; };
 template <>
-struct PassWsMax<float> { static constexpr int M = 4; };
+struct PassWsMax<float> { static constexpr int M = 6; };
 
 // Global offset of tile element e0 = S(first element of LDS slot p); the slot's EPS elements are
 // consecutive in the tile and in vec(rho) (tile bit 0 is global bit 0, and this swizzle never
