@@ -205,16 +205,19 @@ def roofline(prec, k, n, secs):
 
 def roofline_pass(prec, n, secs, m_avg):
     """A pass reads and writes the state once and multiplies it by m_avg 2-qubit
-    superoperators (real-block form: 8 flops per complex MAC, nothing saved): the bound is the
-    resource whose ideal time at its datasheet peak is the longer, the other one beside it."""
+    superoperators (8 algorithmic flops per complex MAC; the kernel's 3M form executes 6): the
+    bound is the resource whose ideal time at its datasheet peak is the longer, the other one
+    beside it."""
     es = 16 if prec == "f64" else 8
     nbytes = 2.0 * (4 ** n) * es
     flops = m_avg * 8.0 * 16 * (4 ** n)
     peak_f = FP64_PEAK_TFLOPS if prec == "f64" else FP32_PEAK_TFLOPS
     gbs = nbytes / secs / 1e9
     tfs = flops / secs / 1e12
+    executed = 0.75 * flops
     common = {"traffic": None, "kernel_k": "pass", "superops_per_launch": round(m_avg, 3),
-              "avg_launch_ms": round(secs * 1e3, 3), "algorithmic_bytes": nbytes, "algorithmic_flops": flops}
+              "avg_launch_ms": round(secs * 1e3, 3), "algorithmic_bytes": nbytes, "algorithmic_flops": flops,
+              "mfma_flops_executed": executed, "mfma_frac_executed": round(executed / secs / 1e12 / peak_f, 4)}
     if nbytes / (HBM_PEAK_GBS * 1e9) >= flops / (peak_f * 1e12):
         return dict({"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(gbs / HBM_PEAK_GBS, 4), "mfma_frac": round(tfs / peak_f, 4)}, **common)

@@ -234,8 +234,9 @@ tanq_status tanq_autotune_dense(tanq_dm d, int reps, double* ms_per_apply);
 /* Multi-superoperator passes.  tanq_apply_fused and tanq_apply_fused_range apply each run of
  * consecutive 2-qubit blocks whose qubits together number at most 6 in one pass over vec(rho):
  * every tile of the state is read into LDS once, multiplied by each superoperator of the run in
- * circuit order (the same per-group arithmetic as a single apply, so the results are bitwise
- * those of applying the blocks one by one), and written back once.  This cuts HBM traffic, the
+ * circuit order (in 3M form: three real products per complex one, where a single apply uses the
+ * real-block form; results agree with applying the blocks one by one to rounding), and written
+ * back once.  This cuts HBM traffic, the
  * bound of 2-qubit applies (Sec. 3.2: a 2-qubit superoperator is memory-bound).  Passes are
  * used on states of at least 10 (FP64) or 11 (FP32) qubits, for runs whose tiles keep whole
  * 128-byte lines of vec(rho), with at most 4 (FP64) or 6 (FP32) superoperators.  With passes
