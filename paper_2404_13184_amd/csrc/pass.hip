@@ -58,7 +58,7 @@ __device__ inline uint64_t pass_tile_base(const PassGeom& g, uint64_t tile) {
 
 }  // namespace
 
-// Superoperators per specialised-wave pass: their operands (1024 elements each) live in LDS
+// Superoperators per specialised-wave pass: their 3M operands (768 elements each) live in LDS
 // beside the two 64 KiB tile buffers.
 template <typename T>
 struct PassWsMax;
