@@ -64,6 +64,10 @@ struct C1Geom {
 // LDS swizzle is the linear map S(e) = e ^ (XOR of xcol[b] over the set bits b of e above the
 // 256-byte bank window).
 constexpr int kPassMax = 8;
+// Pass tiles: 2^12 FP64 or 2^13 FP32 elements (64 KiB); superoperators one pass holds (their
+// 3M operands must fit in LDS beside two tile buffers).
+constexpr int kPassTileBitsF64 = 12, kPassTileBitsF32 = 13;
+constexpr int kPassMaxF64 = 4, kPassMaxF32 = 6;
 struct PassGeom {
   uint64_t ntiles;               // 2^(2n - V)
   int32_t V;                     // tile bits
