@@ -170,6 +170,10 @@ tanq_status tanq_fused_free(tanq_fused f);
  * Blocks are applied in increasing index order; operations inside a block keep circuit
  * order. */
 tanq_status tanq_fuse_plan(tanq_circuit c, int max_width, int* op_block, int* nblocks);
+/* The block assignment tanq_fuse(c, max_width, p) makes under the current pass limit: as
+ * tanq_fuse_plan, then ordered for multi-superoperator passes (commuting blocks moved next to
+ * each other; see tanq_set_pass_limit).  Host only. */
+tanq_status tanq_fuse_plan_ordered(tanq_circuit c, int max_width, tanq_prec p, int* op_block, int* nblocks);
 
 /* Copy fused superoperator idx back to the host: *k, qubits[0..k-1] (ascending) and the
  * FP64 composition S (4^k x 4^k complex128 row-major, caller provides 2*16^k doubles). */

@@ -652,6 +652,19 @@ tanq_status tanq_fuse_plan(tanq_circuit c, int max_width, int* op_block, int* nb
   });
 }
 
+tanq_status tanq_fuse_plan_ordered(tanq_circuit c, int max_width, tanq_prec p, int* op_block, int* nblocks) {
+  return guarded([&] {
+    if (!c || !nblocks) fail(TANQ_E_ARG, "NULL argument");
+    if (max_width < -2 || max_width > 3 || max_width == 0) fail(TANQ_E_ARG, "max_width must be -2, -1, 1, 2 or 3");
+    check_prec(p);
+    if (!c->ops.empty() && !op_block) fail(TANQ_E_ARG, "op_block is NULL");
+    const std::vector<PlanBlock> plan = pass_order(plan_fusion(plan_ops(c->ops), c->n, max_width), c->n, p, pass_limit());
+    for (size_t b = 0; b < plan.size(); ++b)
+      for (int oi : plan[b].ops) op_block[oi] = (int)b;
+    *nblocks = (int)plan.size();
+  });
+}
+
 tanq_status tanq_fused_info(tanq_fused f, tanq_fused_info_t* info) {
   return guarded([&] {
     if (!f || !info) fail(TANQ_E_ARG, "NULL argument");

@@ -43,7 +43,7 @@ EXPORTED = [
     "tanq_variant_count", "tanq_variant_get", "tanq_variant_select", "tanq_variant_selected", "tanq_autotune",
     "tanq_variant_for", "tanq_tuning_export", "tanq_tuning_import", "tanq_autotune_dense",
     "tanq_set_pass_limit", "tanq_get_pass_limit", "tanq_pass_layout_info", "tanq_fused_passes",
-    "tanq_fused_launches",
+    "tanq_fused_launches", "tanq_fuse_plan_ordered",
     "tanq_probs", "tanq_probs_readout", "tanq_sample", "tanq_dm_set_basis", "tanq_reduced_dm",
     "tanq_process_chi_1q",
     "tanq_expect_pauli", "tanq_expect_pauli_c", "tanq_expect_pauli_batch",
@@ -142,6 +142,7 @@ _SIGS = {
     "tanq_pass_layout_info": ([ctypes.c_int, ctypes.c_int, _ip, ctypes.c_int, _ip, _ip], ctypes.c_int),
     "tanq_fused_passes": ([_vp, _ip, _ip], ctypes.c_int),
     "tanq_fused_launches": ([_vp, _ip, ctypes.c_int, _ip], ctypes.c_int),
+    "tanq_fuse_plan_ordered": ([_vp, ctypes.c_int, ctypes.c_int, _ip, _ip], ctypes.c_int),
     "tanq_tuning_export": ([ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "tanq_tuning_import": ([ctypes.c_char_p], ctypes.c_int),
     "tanq_reduced_dm": ([_vp, ctypes.c_int, _ip, _dp], ctypes.c_int),
@@ -307,6 +308,13 @@ def tanq_fuse_plan(circuit: int, max_width: int, nops: int):
     ob = (ctypes.c_int * max(nops, 1))()
     nb = ctypes.c_int()
     _check(load().tanq_fuse_plan(circuit, max_width, ob, ctypes.byref(nb)))
+    return list(ob[:nops]), nb.value
+
+
+def tanq_fuse_plan_ordered(circuit: int, max_width: int, prec, nops: int):
+    ob = (ctypes.c_int * max(nops, 1))()
+    nb = ctypes.c_int()
+    _check(load().tanq_fuse_plan_ordered(circuit, max_width, _prec(prec), ob, ctypes.byref(nb)))
     return list(ob[:nops]), nb.value
 
 
@@ -711,6 +719,10 @@ class Circuit:
 
     def plan(self, max_width: int):
         return tanq_fuse_plan(self.h, max_width, len(self))
+
+    def plan_ordered(self, max_width: int, prec="f64"):
+        """The block assignment fuse() makes: the plan ordered for multi-superoperator passes."""
+        return tanq_fuse_plan_ordered(self.h, max_width, prec, len(self))
 
     def fuse(self, max_width: int = TANQ_FUSE_AUTO, prec="f64", stream=None) -> "Fused":
         return Fused(tanq_fuse(self.h, max_width, _prec(prec), stream))

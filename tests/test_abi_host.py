@@ -196,3 +196,50 @@ def test_pass_layout_rejects_invalid(lib):
             T.tanq_pass_layout_info(16, pairs, "f64")
     with pytest.raises(T.TanqError):  # 2n = 10 < 12 tile bits
         T.tanq_pass_layout_info(5, [(0, 1), (2, 3)], "f64")
+
+
+def _ordered_ok(ops, blocks):
+    """Every pair of operations on a common qubit keeps its circuit order across blocks."""
+    last = {}
+    for i, op in enumerate(ops):
+        for q in op.qubits:
+            if q in last and blocks[last[q]] > blocks[i]:
+                return False
+            last[q] = i
+    return True
+
+
+@pytest.mark.parametrize("prec,n", [("f64", 10), ("f64", 16), ("f32", 11), ("f32", 16)])
+def test_pass_ordering_keeps_dependencies(lib, prec, n):
+    """Ordering blocks for passes only moves blocks past blocks on other qubits: for every qubit
+    the operations on it stay in circuit order, and the blocks are those of the plain plan."""
+    for seed, ops in ((1, W.random_u3_cx(n, 12, 30 + n, 1e-3, 1e-2, gamma=5e-4)),
+                      (2, W.brickwork_cz(n, 12, 40 + n, 1e-3, 1e-2, 1e-3))):
+        c = T.Circuit(n, ops)
+        plain, nb = c.plan(2)
+        ordered, nb2 = c.plan_ordered(2, prec)
+        assert nb2 == nb
+        assert _ordered_ok(ops, ordered)
+        # the same groups of operations, in a different block order
+        groups = lambda bl: sorted(tuple(i for i in range(len(ops)) if bl[i] == b) for b in range(nb))
+        assert groups(plain) == groups(ordered)
+        assert ordered != plain  # passes did reorder something
+        c.free()
+
+
+def test_pass_ordering_off_for_small_states_and_limit_1(lib):
+    n = 8
+    ops = W.random_u3_cx(n, 6, 3, 1e-3, 1e-2)
+    c = T.Circuit(n, ops)
+    assert c.plan_ordered(2, "f64") == c.plan(2)  # 2^(2n-12) < 256 pass tiles
+    c.free()
+    n = 12
+    ops = W.random_u3_cx(n, 6, 3, 1e-3, 1e-2)
+    c = T.Circuit(n, ops)
+    old = T.tanq_get_pass_limit()
+    try:
+        T.tanq_set_pass_limit(1)
+        assert c.plan_ordered(2, "f64") == c.plan(2)
+    finally:
+        T.tanq_set_pass_limit(old)
+    c.free()
