@@ -223,14 +223,16 @@ int pass_run(BlockAt at, int i, int end, int n, tanq_prec p, int lim) {
   return m;
 }
 
-// Reorder a block list so that blocks that can share a pass are adjacent.  From the first
-// block not yet placed, later 1- and 2-qubit blocks (within a short window) join its pass while
-// they fit the pass tile, provided they commute with every block they move ahead of (disjoint
-// qubits); a block that does not join keeps its place and blocks its qubits for the rest of the
-// scan.  One-qubit members of a pass are widened to two qubits (the identity on a qubit the
-// pass already holds), since a pass applies 2-qubit superoperators.  Reordering commuting
-// superoperators leaves the product unchanged.  Returns the list unchanged where passes do
-// not apply.
+// Reorder a block list so that blocks that can share a pass are adjacent.  The first block not
+// yet placed heads a pass.  A scan over the following blocks (within a short window) takes each
+// 1- or 2-qubit block that fits the pass tile and commutes with every block it moves ahead of
+// (shares no qubit with the blocks skipped so far); a skipped block blocks its qubits for the
+// rest of the scan.  The pass's second member decides which blocks fit later, so the scan is
+// repeated with each fitting block forced as the second member and the longest pass is kept.
+// Taken blocks keep their relative order.  One-qubit members of a pass are widened to two
+// qubits (the identity on a qubit the pass already holds), since a pass applies 2-qubit
+// superoperators.  Reordering commuting superoperators leaves the product unchanged.  Returns
+// the list unchanged where passes do not apply.
 std::vector<PlanBlock> pass_order(const std::vector<PlanBlock>& pl, int n, tanq_prec p, int lim) {
   const int V = pass_tile_bits(p);
   const int min_run = p == TANQ_F64 ? 3 : 4;
@@ -244,24 +246,49 @@ std::vector<PlanBlock> pass_order(const std::vector<PlanBlock>& pl, int n, tanq_
   };
   std::vector<int> rem(pl.size());
   for (size_t i = 0; i < rem.size(); ++i) rem[i] = (int)i;
+  auto fits = [&](int b, uint64_t U, uint64_t blocked) {
+    const uint64_t qb = qmask(b);
+    return pl[b].qubits.size() <= 2 && !(qb & blocked) && pass_low_run(U | qb, n, V) >= min_run;
+  };
+  // scan positions after `from`, starting from pass qubits U, taken positions `take` and
+  // blocked qubits; returns the taken positions (increasing) and their qubit union
+  auto scan = [&](size_t from, uint64_t U, uint64_t blocked, std::vector<size_t> take, uint64_t* Uout) {
+    const size_t end = std::min(rem.size(), kWindow);
+    for (size_t pos = from; pos < end && (int)take.size() < lim; ++pos) {
+      const int b = rem[pos];
+      if (fits(b, U, blocked)) {
+        take.push_back(pos);
+        U |= qmask(b);
+      } else {
+        blocked |= qmask(b);
+      }
+    }
+    *Uout = U;
+    return take;
+  };
   std::vector<PlanBlock> out;
   out.reserve(pl.size());
-  std::vector<size_t> take;
   while (!rem.empty()) {
-    take.assign(1, 0);
     const int b0 = rem[0];
+    std::vector<size_t> take(1, 0);
     uint64_t U = qmask(b0);
     if (pl[b0].qubits.size() <= 2) {
+      uint64_t Ub = 0;
+      take = scan(1, U, 0, take, &Ub);
+      U = Ub;
+      // the same scan with each fitting block forced as the second member
       uint64_t blocked = 0;
-      for (size_t pos = 1; pos < rem.size() && pos < kWindow && (int)take.size() < lim; ++pos) {
+      for (size_t pos = 1; pos < std::min(rem.size(), kWindow) && lim >= 3; ++pos) {
         const int b = rem[pos];
-        const uint64_t qb = qmask(b);
-        if (pl[b].qubits.size() <= 2 && !(qb & blocked) && pass_low_run(U | qb, n, V) >= min_run) {
-          take.push_back(pos);
-          U |= qb;
-        } else {
-          blocked |= qb;
+        if (fits(b, qmask(b0), blocked)) {
+          uint64_t Uf = 0;
+          std::vector<size_t> t = scan(pos + 1, qmask(b0) | qmask(b), blocked, std::vector<size_t>{0, pos}, &Uf);
+          if (t.size() > take.size()) {
+            take = std::move(t);
+            U = Uf;
+          }
         }
+        blocked |= qmask(b);
       }
     }
     const bool pass = take.size() >= 2 && __builtin_popcountll(U) >= 2;
