@@ -10,7 +10,8 @@ circuit, so these checks use cases it can compute one output at a time:
 * a noisy circuit confined to four interleaved 4-qubit groups: rho is the tensor product of
   the four 4-qubit oracle results.
 
-All run through the same apply launches (tile shapes, persistent grids) as the benchmark.
+All run through the same apply launches (tile shapes, persistent grids) as the benchmark; at
+fusion width 2 that includes the multi-superoperator pass kernels.
 """
 import sys
 
@@ -70,13 +71,15 @@ def test_single_apply_sampled_groups(oracle_mod, prec, qubits):
         assert checked == 24
 
 
-@pytest.mark.parametrize("mode,prec", [(2, "f64"), (3, "f64"), (3, "f32")])
+@pytest.mark.parametrize("mode,prec", [(2, "f64"), (2, "f32"), (3, "f64"), (3, "f32")])
 def test_noiseless_circuit_vs_statevector(oracle_mod, mode, prec):
     ops = W.random_u3_cx(N, 6, seed=44, p1=0.0, p2=0.0)
     psi = oracle_mod.statevector(N, ops)
     say("n=16 noiseless mode=%d %s" % (mode, prec))
     c = T.Circuit(N, ops)
     f = c.fuse(mode, prec)
+    if mode == 2:
+        assert f.passes()[0] > 0  # width 2 runs as multi-superoperator passes, as in the benchmark
     rng = np.random.default_rng(3)
     with T.DM(N, prec) as d:
         d.apply_fused(f)
