@@ -7,6 +7,7 @@
 #include <mutex>
 #include <algorithm>
 #include <cstring>
+#include <deque>
 #include <map>
 #include <memory>
 #include <string>
@@ -244,7 +245,9 @@ std::vector<PlanBlock> pass_order(const std::vector<PlanBlock>& pl, int n, tanq_
     for (int q : pl[b].qubits) m |= 1ull << q;
     return m;
   };
-  std::vector<int> rem(pl.size());
+  // blocks not yet placed; taken blocks lie within the window at the front, where a deque
+  // erases in constant time
+  std::deque<int> rem(pl.size());
   for (size_t i = 0; i < rem.size(); ++i) rem[i] = (int)i;
   auto fits = [&](int b, uint64_t U, uint64_t blocked) {
     const uint64_t qb = qmask(b);
