@@ -616,6 +616,72 @@ def teleport_layers(n: int, layers: int, seed: int, p1: float, p2: float) -> Lis
     return ops
 
 
+# --------------------------------------------------------------------------------------
+# Nested entanglement purification (the distillation case study, Sec. 5; the protocol of
+# Deutsch et al. 1996)
+# --------------------------------------------------------------------------------------
+
+
+def agree_projector() -> List[np.ndarray]:
+    """Post-selection on equal Z outcomes of a qubit pair: the single Kraus operator
+    |00><00| + |11><11|.  It is not trace preserving: after it, the trace of the state is the
+    probability that the two measurements agreed."""
+    return [np.diag([1.0, 0.0, 0.0, 1.0]).astype(np.complex128)]
+
+
+def werner_pair(a: int, b: int, fidelity: float) -> List[Op]:
+    """The Bell pair |Phi+> on (a, b) degraded to a Werner state of the given fidelity with
+    |Phi+>: H(a), CX(a, b), then one-qubit depolarizing p = 4 (1 - F) / 3 on b (which keeps
+    |Phi+> with weight 1 - 3p/4 and gives each other Bell state p/4)."""
+    if not 0.25 <= fidelity <= 1.0:
+        raise ValueError("Werner fidelity must lie in [1/4, 1]")
+    ops = [gate(hadamard(), (a,), "h"), gate(cx(), (a, b), "cx")]
+    p = 4.0 * (1.0 - fidelity) / 3.0
+    if p > 0:
+        ops.append(channel(depolarizing(p, 1), (b,), "werner"))
+    return ops
+
+
+def purify_step(control: Tuple[int, int], target: Tuple[int, int], cx_error: float) -> List[Op]:
+    """One purification step on two pairs, each given as (Alice's qubit, Bob's qubit):
+    Rx(pi/2) on Alice's qubits and Rx(-pi/2) on Bob's, a CX from the control pair to the
+    target pair on each side (each followed by two-qubit depolarizing cx_error when it is
+    positive), then the target pair is measured in Z and kept only when both outcomes agree
+    (agree_projector)."""
+    (ac, bc), (at, bt) = control, target
+    ops: List[Op] = []
+    for q in (ac, at):
+        ops.append(gate(rx(math.pi / 2), (q,), "rx"))
+    for q in (bc, bt):
+        ops.append(gate(rx(-math.pi / 2), (q,), "rx"))
+    for c_, t_ in ((ac, at), (bc, bt)):
+        ops.append(gate(cx(), (c_, t_), "cx"))
+        if cx_error > 0:
+            ops.append(channel(depolarizing(cx_error, 2), (c_, t_), "dep2"))
+    ops.append(channel(agree_projector(), (at, bt), "agree"))
+    return ops
+
+
+def nested_purification(rounds: int, fidelity: float, cx_error: float) -> Tuple[int, List[Op]]:
+    """2^rounds Werner pairs of the given fidelity purified in `rounds` nested rounds down to
+    one pair on qubits (0, 1).  Pair i sits on qubits (2i, 2i + 1) (Alice, Bob).  Round r
+    (from 1) purifies pair i (control) with pair i + 2^(r-1) (target) for every i that is a
+    multiple of 2^r.  The trace of the final state is the probability that every step
+    succeeded, and the kept pair's fidelity is <Phi+| rho_01 |Phi+> divided by that trace."""
+    if rounds < 1:
+        raise ValueError("at least one round")
+    npairs = 1 << rounds
+    ops: List[Op] = []
+    for i in range(npairs):
+        ops.extend(werner_pair(2 * i, 2 * i + 1, fidelity))
+    for r in range(1, rounds + 1):
+        half = 1 << (r - 1)
+        for i in range(0, npairs, 1 << r):
+            j = i + half
+            ops.extend(purify_step((2 * i, 2 * i + 1), (2 * j, 2 * j + 1), cx_error))
+    return 2 * npairs, ops
+
+
 @dataclasses.dataclass
 class Request:
     rid: int
