@@ -125,7 +125,9 @@ tanq_status tanq_circuit_free(tanq_circuit c);
 tanq_status tanq_circuit_add_gate(tanq_circuit c, int j, const int* qubits, const double* U);
 
 /* Append a j-qubit channel given by m >= 1 Kraus matrices K (m consecutive 2^j x 2^j
- * complex128 row-major matrices).  The channel is rho -> sum_i K_i rho K_i^dagger. */
+ * complex128 row-major matrices).  The channel is rho -> sum_i K_i rho K_i^dagger.  The set
+ * need not be trace preserving: a post-selection (a projector) lowers the trace to the
+ * probability of the selected outcomes, which tanq_probs reports as the trace. */
 tanq_status tanq_circuit_add_kraus(tanq_circuit c, int j, const int* qubits, int m, const double* K);
 
 /* Append `count` operations at once.  Operation i acts on qubits[3i .. 3i + j[i] - 1] with
