@@ -24,14 +24,14 @@ def say(*a):
     sys.stdout.flush()
 
 
-def run_fused(n, ops, prec, limit, rho_in=None, fuse_limit=8):
-    """Fuse at width 2 under pass limit fuse_limit (which orders the blocks for passes), then
-    apply under pass limit `limit` (1 = every block on its own)."""
+def run_fused(n, ops, prec, limit, rho_in=None, fuse_limit=8, width=2):
+    """Fuse at the given width under pass limit fuse_limit (which orders the blocks for
+    passes), then apply under pass limit `limit` (1 = every block on its own)."""
     old = T.tanq_get_pass_limit()
     try:
         T.tanq_set_pass_limit(fuse_limit)
         c = T.Circuit(n, ops)
-        f = c.fuse(2, prec)
+        f = c.fuse(width, prec)
         T.tanq_set_pass_limit(limit)
         passes = f.passes()
         d = T.DM(n, prec)
@@ -70,15 +70,27 @@ def test_passes_match_single_applies(prec, n):
         assert close(got, want, prec)
 
 
+@pytest.mark.parametrize("prec,n", [("f64", 10), ("f32", 11)])
 @pytest.mark.parametrize("limit", [2, 3, 5])
-def test_pass_limits(limit):
-    n = 10
+def test_pass_limits(prec, n, limit):
     ops = W.random_u3_cx(n, 5, 3, 1e-3, 1e-2)
-    say("pass limit %d" % limit)
-    want, _ = run_fused(n, ops, "f64", 1)
-    got, (np_, nin) = run_fused(n, ops, "f64", limit)
+    say("pass limit %d %s n=%d" % (limit, prec, n))
+    want, _ = run_fused(n, ops, prec, 1)
+    got, (np_, nin) = run_fused(n, ops, prec, limit)
     assert np_ > 0 and nin <= limit * np_
-    assert close(got, want, "f64")
+    assert close(got, want, prec)
+
+
+@pytest.mark.parametrize("prec,n", [("f64", 11), ("f32", 12)])
+def test_passes_in_width_3_plans(prec, n):
+    """A width-3 plan mixes 3-qubit blocks (single applies) with runs of 2-qubit blocks that
+    form passes; the two kinds must interleave in circuit order."""
+    ops = W.random_u3_cx(n, 6, 17 + n, 1e-3, 1e-2, gamma=5e-4)
+    say("passes in a width-3 plan %s n=%d" % (prec, n))
+    want, _ = run_fused(n, ops, prec, 1, width=3)
+    got, (np_, _) = run_fused(n, ops, prec, 8, width=3)
+    assert np_ > 0
+    assert close(got, want, prec)
 
 
 def test_passes_match_oracle_f64(oracle_mod):
