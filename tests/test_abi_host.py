@@ -243,3 +243,57 @@ def test_pass_ordering_off_for_small_states_and_limit_1(lib):
     finally:
         T.tanq_set_pass_limit(old)
     c.free()
+
+
+def _pass_runs(n, ops, blocks, nb, tile_bits, min_run, lim):
+    """Lengths of the launches the ordered plan makes: consecutive blocks of at most two qubits
+    form one pass while their qubits' row and column bits, filled up with the lowest other bits
+    to tile_bits, keep global bits 0..min_run-1 inside the tile (whole 128-byte lines)."""
+    qs = [set() for _ in range(nb)]
+    for op, b in zip(ops, blocks):
+        qs[b] |= set(op.qubits)
+
+    def low_run(U):
+        held = set(U) | {q + n for q in U}
+        fill = tile_bits - len(held)
+        if fill < 0:
+            return -1
+        b = 0
+        while fill > 0:
+            if b not in held:
+                held.add(b)
+                fill -= 1
+            b += 1
+        c = 0
+        while c in held:
+            c += 1
+        return c
+
+    runs, i = [], 0
+    while i < nb:
+        U, m = set(), 0
+        while i + m < nb and m < lim and len(qs[i + m]) <= 2 and low_run(U | qs[i + m]) >= min_run:
+            U |= qs[i + m]
+            m += 1
+        m = max(m, 1)
+        runs.append(m)
+        i += m
+    return runs
+
+
+def test_pass_grouping_on_the_benchmark_circuit(lib):
+    """The 16-qubit, 100-layer benchmark circuit at fusion width 2: the ordered plan puts its 761
+    blocks into at most 205 FP64 passes (limit 4) and 190 FP32 passes (limit 6), i.e. about
+    3.75 and 4.1 superoperators per pass; trying each second member is what gets there (the
+    first-fit scan alone gives 248 and 226)."""
+    n, ops = W.config4(layers=100, n=16)
+    c = T.Circuit(n, ops)
+    try:
+        for prec, V, min_run, lim, most in (("f64", 12, 3, 4, 205), ("f32", 13, 4, 6, 190)):
+            blocks, nb = c.plan_ordered(2, prec)
+            assert nb == 761
+            runs = _pass_runs(n, ops, blocks, nb, V, min_run, lim)
+            assert sum(runs) == nb and max(runs) <= lim
+            assert len(runs) <= most, (prec, len(runs))
+    finally:
+        c.free()
