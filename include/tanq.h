@@ -88,6 +88,13 @@ tanq_status tanq_dm_free(tanq_dm d);
 /* rho = |0..0><0..0| (stream-ordered). */
 tanq_status tanq_dm_reset(tanq_dm d);
 
+/* rho <- factor * rho in place (stream-ordered), e.g. factor = 1/tr to renormalise the state
+ * itself rather than its outputs.  Every element is read once and written once with 16-byte
+ * accesses and nothing else, so the call is also the plain in-place streaming pass over the
+ * state buffer against which the apply kernels' bandwidth is measured.  TANQ_E_ARG if factor
+ * is not finite.  In FP32 the factor is rounded to float. */
+tanq_status tanq_dm_scale(tanq_dm d, double factor);
+
 /* Number of qubits, precision, element count (4^n) and device pointer of a handle. */
 tanq_status tanq_dm_query(tanq_dm d, int* n, int* prec, uint64_t* elements, void** dev_ptr);
 

@@ -371,6 +371,15 @@ tanq_status tanq_dm_reset(tanq_dm d) {
   });
 }
 
+tanq_status tanq_dm_scale(tanq_dm d, double factor) {
+  return guarded([&] {
+    check_dm(d);
+    if (!std::isfinite(factor)) fail(TANQ_E_ARG, "scale factor must be finite");
+    DeviceGuard g(d->device);
+    launch_scale(d->ptr, d->n, d->prec, factor, d->stream);
+  });
+}
+
 tanq_status tanq_dm_query(tanq_dm d, int* n, int* prec, uint64_t* elements, void** dev_ptr) {
   return guarded([&] {
     check_dm(d);

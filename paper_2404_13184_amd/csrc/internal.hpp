@@ -162,6 +162,7 @@ void launch_init_zero(void* rho, int n, tanq_prec p, hipStream_t s);
 void launch_gather(const void* rho, tanq_prec p, const uint64_t* idx_dev, size_t count, void* out_dev,
                    hipStream_t s);
 void launch_fill_random(void* rho, int n, tanq_prec p, uint64_t seed, hipStream_t s);
+void launch_scale(void* rho, int n, tanq_prec p, double f, hipStream_t s);
 
 // Apply one superoperator whose packed operand is at `packed` (device).
 //   k == 1: packed = 4x4 complex FP64 (32 doubles), used for both precisions.

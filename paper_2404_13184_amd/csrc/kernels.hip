@@ -48,6 +48,30 @@ __global__ void fill_random_kernel(T* __restrict__ rho, uint64_t nel, uint64_t s
   }
 }
 
+// rho <- f rho in place: every element read once and written once with 16-byte accesses
+// (one FP64 or two FP32 complex values per access).  Each thread loads U accesses spaced one
+// workgroup apart before it stores any of them, so a wave keeps U loads in flight; the grid
+// strides over the state.  This is the plain streaming kernel of the state buffer (one read
+// and one write of every element, nothing else), so its rate is the bandwidth that any
+// in-place pass over vec(rho) can reach.
+template <typename V, typename S, int U>
+__global__ __launch_bounds__(256) void scale_kernel(V* __restrict__ x, uint64_t nvec, S f) {
+  const uint64_t stride = (uint64_t)gridDim.x * (256 * U);
+  for (uint64_t base = (uint64_t)blockIdx.x * (256 * U) + threadIdx.x; base < nvec; base += stride) {
+    V v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint64_t i = base + (uint64_t)u * 256;
+      if (i < nvec) v[u] = x[i];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint64_t i = base + (uint64_t)u * 256;
+      if (i < nvec) x[i] = v[u] * f;
+    }
+  }
+}
+
 template <typename T>
 __global__ void gather_kernel(const T* __restrict__ rho, const uint64_t* __restrict__ idx, uint64_t count,
                               T* __restrict__ out) {
@@ -445,6 +469,22 @@ void launch_fill_random(void* rho, int n, tanq_prec p, uint64_t seed, hipStream_
     hipLaunchKernelGGL(fill_random_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, s, (double*)rho, nel, seed);
   else
     hipLaunchKernelGGL(fill_random_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, s, (float*)rho, nel, seed);
+  TANQ_HIP(hipGetLastError());
+}
+
+void launch_scale(void* rho, int n, tanq_prec p, double f, hipStream_t s) {
+  constexpr int U = 4;
+  // 16-byte accesses: one FP64 complex element, or two FP32 ones
+  const uint64_t nvec = (p == TANQ_F64) ? (1ull << (2 * n)) : (1ull << (2 * n)) / 2;
+  uint64_t blocks = (nvec + 256 * U - 1) / (256 * U);
+  const uint64_t cap = (uint64_t)device_cu_count() * 16;
+  if (blocks > cap) blocks = cap;
+  if (p == TANQ_F64)
+    hipLaunchKernelGGL((scale_kernel<f64x2, double, U>), dim3((unsigned)blocks), dim3(256), 0, s, (f64x2*)rho,
+                       nvec, f);
+  else
+    hipLaunchKernelGGL((scale_kernel<f32x4, float, U>), dim3((unsigned)blocks), dim3(256), 0, s, (f32x4*)rho,
+                       nvec, (float)f);
   TANQ_HIP(hipGetLastError());
 }
 

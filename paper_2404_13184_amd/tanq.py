@@ -35,7 +35,7 @@ TANQ_FUSE_PAPER = -2
 EXPORTED = [
     "tanq_last_error", "tanq_version",
     "tanq_dm_init", "tanq_dm_wrap", "tanq_dm_free", "tanq_dm_reset", "tanq_dm_query",
-    "tanq_dm_read", "tanq_dm_write", "tanq_dm_fill_random", "tanq_dm_gather", "tanq_sync",
+    "tanq_dm_read", "tanq_dm_write", "tanq_dm_fill_random", "tanq_dm_gather", "tanq_sync", "tanq_dm_scale",
     "tanq_circuit_create", "tanq_circuit_free", "tanq_circuit_add_gate", "tanq_circuit_add_kraus",
     "tanq_circuit_add_ops", "tanq_circuit_size",
     "tanq_fuse", "tanq_fuse_plan", "tanq_fused_info", "tanq_fused_free", "tanq_fused_get",
@@ -152,6 +152,7 @@ _SIGS = {
     "tanq_expect_pauli_c": ([_vp, ctypes.c_char_p, _dp, _dp], ctypes.c_int),
     "tanq_expect_pauli_batch": ([_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_char_p), _dp, _dp], ctypes.c_int),
     "tanq_dm_compare": ([_vp, _vp, _dp], ctypes.c_int),
+    "tanq_dm_scale": ([_vp, ctypes.c_double], ctypes.c_int),
     "tanq_server_create": ([ctypes.POINTER(ServerConfig), ctypes.POINTER(_vp)], ctypes.c_int),
     "tanq_server_submit": ([_vp, _vp, ctypes.POINTER(Outputs), ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
     "tanq_server_poll": ([_vp, ctypes.c_uint64, ctypes.POINTER(Result)], ctypes.c_int),
@@ -229,6 +230,10 @@ def tanq_dm_free(h: int):
 
 def tanq_dm_reset(h: int):
     _check(load().tanq_dm_reset(h))
+
+
+def tanq_dm_scale(h: int, factor: float):
+    _check(load().tanq_dm_scale(h, float(factor)))
 
 
 def tanq_dm_query(h: int):
@@ -623,6 +628,9 @@ class DM:
 
     def reset(self):
         tanq_dm_reset(self.h)
+
+    def scale(self, factor: float):
+        tanq_dm_scale(self.h, factor)
 
     def read(self) -> np.ndarray:
         out = np.empty(4 ** self.n, dtype=self.dtype)

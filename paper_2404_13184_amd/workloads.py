@@ -298,6 +298,13 @@ def dephase() -> List[np.ndarray]:
     return [np.diag([1.0, 0.0]).astype(np.complex128), np.diag([0.0, 1.0]).astype(np.complex128)]
 
 
+def reset() -> List[np.ndarray]:
+    """Reset to |0> (Sec. 3, measurement and reset as operations of their own): the Kraus set
+    {|0><0|, |0><1|}, i.e. a Z measurement whose outcome is discarded followed by a flip to
+    |0> where 1 was read.  On qubit q it maps rho to Tr_q(rho) (x) |0><0|_q; trace preserving."""
+    return [np.array([[1, 0], [0, 0]], dtype=np.complex128), np.array([[0, 1], [0, 0]], dtype=np.complex128)]
+
+
 # --------------------------------------------------------------------------------------
 # Device calibration and noise injection into basis circuits (Sec. 3.5, Sec. 4)
 # --------------------------------------------------------------------------------------
@@ -506,6 +513,20 @@ def random_u3_cx(n: int, layers: int, seed: int, p1: float, p2: float,
             ops.append(gate(cx(), (c, t), "cx"))
             if dep2 is not None:
                 ops.append(channel(dep2, (c, t), "dep2"))
+    return ops
+
+
+def random_u3_cx_reset(n: int, layers: int, seed: int, p1: float, p2: float,
+                       resets_per_layer: int = 1) -> List[Op]:
+    """:func:`random_u3_cx` with mid-circuit resets (ancilla reuse): after each layer's CX
+    gates, ``resets_per_layer`` distinct random qubits are reset to |0> (:func:`reset`)."""
+    rng = np.random.default_rng(seed)
+    ops: List[Op] = []
+    rst = reset()
+    for layer in range(layers):
+        ops.extend(random_u3_cx(n, 1, int(rng.integers(0, 2 ** 31)), p1, p2))
+        for q in rng.choice(n, size=min(resets_per_layer, n), replace=False):
+            ops.append(channel(rst, (int(q),), "reset"))
     return ops
 
 

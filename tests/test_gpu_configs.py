@@ -10,6 +10,7 @@ FP64 states), checked where the oracle cannot hold the whole run:
   elements follow from single-qubit oracle runs;
 * FP64 results under different fusion widths agree (consistency of the fused path).
 """
+import os
 import sys
 
 import numpy as np
@@ -152,3 +153,42 @@ def test_ising_15q_full_size_widths_agree():
     a.free()
     b.free()
     c.free()
+
+
+GOLDEN_BRICK = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "brickwork14_2layers.npz")
+
+
+@pytest.mark.parametrize("prec,width", [("f64", 2), ("f64", 3), ("f32", 2)])
+def test_brickwork_14q_prefix_against_oracle(prec, width):
+    """The first two layers of the noisy 14-qubit brickwork (every bond entangled once, all
+    noise channels present) against the oracle's result, written by tests/golden/make_golden.py:
+    all 2^14 probabilities, 4096 sampled elements of vec(rho) and <Z_i Z_i+1>.  FP64 runs as
+    passes at width 2 and as 3-qubit applies at width 3."""
+    if not os.path.exists(GOLDEN_BRICK):
+        pytest.skip("oracle values not generated (tests/golden/make_golden.py brickwork)")
+    g = np.load(GOLDEN_BRICK)
+    n, ops = W.config2(layers=2)
+    say("brickwork n=14 2-layer prefix vs oracle: %s width %d" % (prec, width))
+    c = T.Circuit(n, ops)
+    f = c.fuse(width, prec)
+    if prec == "f64" and width == 2:
+        assert f.passes()[0] > 0
+    d = T.DM(n, prec)
+    d.apply_fused(f)
+    p, tr = d.probs(renormalize=True)
+    vals = d.gather(g["idx"]).astype(np.complex128)
+    zz = np.real(d.expect_paulis(W.zz_paulis(n)))
+    d.free()
+    f.free()
+    c.free()
+    if prec == "f64":
+        assert np.abs(vals - g["val"]).max() <= 1e-10
+        assert np.linalg.norm(vals - g["val"]) <= 1e-12 * np.linalg.norm(g["val"])
+        assert np.abs(p - g["probs"]).max() <= 1e-12
+        assert abs(tr - float(g["trace"])) <= 1e-12
+        assert np.abs(zz - g["zz"]).max() <= 1e-12
+    else:
+        assert np.abs(p - g["probs"]).max() <= 1e-5
+        assert np.abs(vals - g["val"]).max() <= 1e-6
+        assert abs(tr - float(g["trace"])) <= 1e-5
+        assert np.abs(zz - g["zz"]).max() <= 1e-5

@@ -403,3 +403,26 @@ def test_three_qubit_operations_fused(oracle_mod, prec):
             check64(got, want, "mode %d" % mode)
         else:
             assert oracle_mod.trace_distance(got / np.trace(got), want / np.trace(want)) <= 1e-4
+
+
+# ---------------------------------------------------------------------------------------
+# in-place scaling (the plain streaming pass over the state)
+# ---------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("n", [1, 2, 4, 5, 9, 12])
+def test_scale_in_place(prec, n):
+    """Partial workgroups (n <= 4), one exact workgroup (n = 5 FP64) and grid-stride sweeps
+    (n = 12): every element equals the host product in the state's precision."""
+    say("scale n=%d %s" % (n, prec))
+    with T.DM(n, prec) as d:
+        d.fill_random(3 + n)
+        x = d.read()
+        for f in (0.5, 1.0 / 3.0, -2.0):
+            d.scale(f)
+            ft = x.real.dtype.type(f)
+            x = (x.real * ft + 1j * (x.imag * ft)).astype(x.dtype)
+            got = d.read()
+            assert np.array_equal(got, x), (n, prec, f)
+        with pytest.raises(T.TanqError):
+            d.scale(float("inf"))

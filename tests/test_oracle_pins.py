@@ -254,6 +254,65 @@ def test_thermal_relaxation_decay(oracle_mod):
         assert abs(rho[0, 1] - rho0[0, 1] * math.exp(-m * t / t2)) <= TOL
 
 
+def reset_closed_form(rho, n, q):
+    """Tr_q(rho) (x) |0><0|_q by tensor reshaping: qubit q is bit q of the index, i.e. axis
+    n - 1 - q of the C-ordered (2,)*n row and column shape."""
+    t = rho.reshape((2,) * (2 * n))
+    ar, ac = n - 1 - q, 2 * n - 1 - q
+    red = np.trace(t, axis1=ar, axis2=ac)  # the other qubits' axes, rows then columns
+    out = np.zeros_like(t)
+    idx = [slice(None)] * (2 * n)
+    idx[ar] = 0
+    idx[ac] = 0
+    out[tuple(idx)] = red
+    return out.reshape(1 << n, 1 << n)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4])
+def test_reset_closed_form(oracle_mod, n):
+    """Reset of qubit q leaves Tr_q(rho) (x) |0><0|_q on every qubit of random states and of
+    non-Hermitian inputs (the map is linear), and keeps the trace."""
+    rng = np.random.default_rng(40 + n)
+    for q in range(n):
+        for rho in (random_density(rng, n), random_matrix(rng, 1 << n)):
+            got = oracle_mod.run(n, [W.channel(W.reset(), (q,))], rho)
+            want = reset_closed_form(rho, n, q)
+            assert np.abs(got - want).max() <= TOL * max(1.0, np.abs(want).max()), q
+            assert abs(np.trace(got) - np.trace(rho)) <= TOL * max(1.0, abs(np.trace(rho)))
+
+
+def test_reset_special_cases(oracle_mod):
+    """|1..1> reset qubit by qubit ends in |0..0>; a reset is idempotent; reset of one half of a
+    Bell pair leaves I/2 on the other half (the reduced state of a maximally entangled pair)."""
+    n = 3
+    flip = [W.gate(W.u3(math.pi, 0.0, 0.0), (q,)) for q in range(n)]
+    rho = oracle_mod.run(n, flip + [W.channel(W.reset(), (q,)) for q in range(n)])
+    want = np.zeros((1 << n, 1 << n))
+    want[0, 0] = 1.0
+    assert np.abs(rho - want).max() <= TOL
+    rng = np.random.default_rng(5)
+    r0 = random_density(rng, n)
+    once = oracle_mod.run(n, [W.channel(W.reset(), (1,))], r0)
+    twice = oracle_mod.run(n, [W.channel(W.reset(), (1,))] * 2, r0)
+    assert np.abs(once - twice).max() <= TOL
+    bell = [W.gate(W.hadamard(), (0,)), W.gate(W.cx(), (0, 1)), W.channel(W.reset(), (0,))]
+    rho = oracle_mod.run(2, bell)
+    # qubit 0 in |0>, qubit 1 maximally mixed: diag over index b0 + 2 b1 is (1/2, 0, 1/2, 0)
+    assert np.abs(rho - np.diag([0.5, 0.0, 0.5, 0.0])).max() <= TOL
+
+
+def test_reset_brute_force(oracle_mod):
+    """Reset inside a noisy circuit against the Kronecker construction."""
+    n = 3
+    ops = W.random_u3_cx_reset(n, 3, seed=8, p1=0.02, p2=0.05, resets_per_layer=2)
+    assert sum(op.label == "reset" for op in ops) == 6
+    rho_in = np.zeros((1 << n, 1 << n), dtype=np.complex128)
+    rho_in[0, 0] = 1
+    got = oracle_mod.run(n, ops)
+    want = brute_run(n, ops, rho_in)
+    assert np.abs(got - want).max() <= TOL
+
+
 PHI_PLUS = np.array([1, 0, 0, 1], dtype=np.complex128) / math.sqrt(2)
 
 
