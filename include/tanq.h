@@ -315,6 +315,15 @@ tanq_status tanq_probs_readout(tanq_dm d, const double* p01, const double* p10, 
 tanq_status tanq_sample(tanq_dm d, uint64_t shots, uint64_t seed, const double* p01, const double* p10,
                         uint64_t* host_out);
 
+/* tanq_sample without any device allocation, for callers that cannot allocate: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same arguments, draws
+ * and outcomes as tanq_sample.  The CDF and the outcomes live in a fixed 2 MiB device array of
+ * the library (one per GPU, held until the process ends), so n <= 17 and shots <= 2^17 per call;
+ * beyond that TANQ_E_ARG.  Calls on one GPU share that array: calls that overlap there (from
+ * several threads, or on streams that are not drained in between) race.  Synchronises. */
+tanq_status tanq_sample_noalloc(tanq_dm d, uint64_t shots, uint64_t seed, const double* p01, const double* p10,
+                                uint64_t* host_out);
+
 /* rho = |r><c| (a basis operator; not a state unless r == c).  Input of process tomography,
  * where the channel is linear in its input.  Stream-ordered. */
 tanq_status tanq_dm_set_basis(tanq_dm d, uint64_t r, uint64_t c);

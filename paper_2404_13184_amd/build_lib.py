@@ -15,7 +15,7 @@ ROOT = os.path.dirname(PKG)
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libtanq.so")
 
-SOURCES = ["apply.hip", "batch.hip", "pass.hip", "pass_geom.cpp", "kernels.hip", "api.cpp", "fuse_plan.cpp", "circuit.cpp", "serve.cpp"]
+SOURCES = ["apply.hip", "batch.hip", "pass.hip", "pass_geom.cpp", "kernels.hip", "noalloc.hip", "api.cpp", "fuse_plan.cpp", "circuit.cpp", "serve.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 COMMON = [

@@ -1238,26 +1238,48 @@ tanq_status tanq_probs_readout(tanq_dm d, const double* p01, const double* p10, 
   });
 }
 
+}  // extern "C"
+
+namespace tanq {
+
+void sample_check(tanq_dm d, uint64_t shots, uint64_t seed, const double* p01, const double* p10, uint64_t* host_out,
+                  int* n, int* device) {
+  check_dm(d);
+  if (shots > 0 && !host_out) fail(TANQ_E_ARG, "NULL argument");
+  if (seed >= (1ull << 23)) fail(TANQ_E_ARG, "seed must be below 2^23");
+  if (shots > (1ull << 40)) fail(TANQ_E_ARG, "too many shots");
+  check_readout(d->n, p01, p10);
+  *n = d->n;
+  *device = d->device;
+}
+
+void sample_run(tanq_dm d, uint64_t shots, uint64_t seed, const double* p01, const double* p10, double* cdf_dev,
+                uint64_t* out_dev, uint64_t* host_out) {
+  DeviceGuard g(d->device);
+  launch_diag(d->ptr, d->n, d->prec, d->probs_dev, d->partials, d->result_dev, 1, d->stream);
+  if (p01) launch_readout(d->probs_dev, d->n, p01, p10, d->stream);
+  launch_sample(d->probs_dev, d->n, cdf_dev, shots, seed, out_dev, d->stream);
+  TANQ_HIP(hipMemcpyAsync(host_out, out_dev, shots * sizeof(uint64_t), hipMemcpyDeviceToHost, d->stream));
+  TANQ_HIP(hipStreamSynchronize(d->stream));
+}
+
+}  // namespace tanq
+
+extern "C" {
+
 tanq_status tanq_sample(tanq_dm d, uint64_t shots, uint64_t seed, const double* p01, const double* p10,
                         uint64_t* host_out) {
   return guarded([&] {
-    check_dm(d);
+    int n = 0, device = 0;
+    sample_check(d, shots, seed, p01, p10, host_out, &n, &device);
     if (shots == 0) return;
-    if (!host_out) fail(TANQ_E_ARG, "NULL argument");
-    if (seed >= (1ull << 23)) fail(TANQ_E_ARG, "seed must be below 2^23");
-    if (shots > (1ull << 40)) fail(TANQ_E_ARG, "too many shots");
-    check_readout(d->n, p01, p10);
-    DeviceGuard g(d->device);
+    DeviceGuard g(device);
     double* cdf = nullptr;
     uint64_t* out = nullptr;
     try {
-      TANQ_HIP(hipMalloc((void**)&cdf, (1ull << d->n) * sizeof(double)));
+      TANQ_HIP(hipMalloc((void**)&cdf, (1ull << n) * sizeof(double)));
       TANQ_HIP(hipMalloc((void**)&out, shots * sizeof(uint64_t)));
-      launch_diag(d->ptr, d->n, d->prec, d->probs_dev, d->partials, d->result_dev, 1, d->stream);
-      if (p01) launch_readout(d->probs_dev, d->n, p01, p10, d->stream);
-      launch_sample(d->probs_dev, d->n, cdf, shots, seed, out, d->stream);
-      TANQ_HIP(hipMemcpyAsync(host_out, out, shots * sizeof(uint64_t), hipMemcpyDeviceToHost, d->stream));
-      TANQ_HIP(hipStreamSynchronize(d->stream));
+      sample_run(d, shots, seed, p01, p10, cdf, out, host_out);
     } catch (...) {
       (void)hipStreamSynchronize(d->stream);
       dfree(cdf);

@@ -164,6 +164,14 @@ void launch_gather(const void* rho, tanq_prec p, const uint64_t* idx_dev, size_t
 void launch_fill_random(void* rho, int n, tanq_prec p, uint64_t seed, hipStream_t s);
 void launch_scale(void* rho, int n, tanq_prec p, double f, hipStream_t s);
 
+// All-qubit sampling (tanq_sample and its variant without allocations): argument checks (also
+// returning the handle's qubit count and device), and the work itself on the caller's device
+// buffers for the CDF (2^n doubles) and the outcomes (shots words); synchronises.
+void sample_check(tanq_dm d, uint64_t shots, uint64_t seed, const double* p01, const double* p10, uint64_t* host_out,
+                  int* n, int* device);
+void sample_run(tanq_dm d, uint64_t shots, uint64_t seed, const double* p01, const double* p10, double* cdf_dev,
+                uint64_t* out_dev, uint64_t* host_out);
+
 // Apply one superoperator whose packed operand is at `packed` (device).
 //   k == 1: packed = 4x4 complex FP64 (32 doubles), used for both precisions.
 //   k == 2, 3: packed = real-block fragments in precision p.

@@ -44,7 +44,7 @@ EXPORTED = [
     "tanq_variant_for", "tanq_tuning_export", "tanq_tuning_import", "tanq_autotune_dense",
     "tanq_set_pass_limit", "tanq_get_pass_limit", "tanq_pass_layout_info", "tanq_fused_passes",
     "tanq_fused_launches", "tanq_fuse_plan_ordered",
-    "tanq_probs", "tanq_probs_readout", "tanq_sample", "tanq_dm_set_basis", "tanq_reduced_dm",
+    "tanq_probs", "tanq_probs_readout", "tanq_sample", "tanq_sample_noalloc", "tanq_dm_set_basis", "tanq_reduced_dm",
     "tanq_process_chi_1q",
     "tanq_expect_pauli", "tanq_expect_pauli_c", "tanq_expect_pauli_batch",
     "tanq_dm_compare",
@@ -148,6 +148,8 @@ _SIGS = {
     "tanq_reduced_dm": ([_vp, ctypes.c_int, _ip, _dp], ctypes.c_int),
     "tanq_process_chi_1q": ([_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _dp], ctypes.c_int),
     "tanq_sample": ([_vp, ctypes.c_uint64, ctypes.c_uint64, _dp, _dp, ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
+    "tanq_sample_noalloc": ([_vp, ctypes.c_uint64, ctypes.c_uint64, _dp, _dp, ctypes.POINTER(ctypes.c_uint64)],
+                            ctypes.c_int),
     "tanq_expect_pauli": ([_vp, ctypes.c_char_p, _dp], ctypes.c_int),
     "tanq_expect_pauli_c": ([_vp, ctypes.c_char_p, _dp, _dp], ctypes.c_int),
     "tanq_expect_pauli_batch": ([_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_char_p), _dp, _dp], ctypes.c_int),
@@ -487,16 +489,24 @@ def tanq_process_chi_1q(circuit: int, max_width: int, prec, in_qubit: int, out_q
     return chi, S
 
 
-def tanq_sample(h: int, shots: int, seed: int, p01=None, p10=None) -> np.ndarray:
+def _sample_call(fn, h: int, shots: int, seed: int, p01=None, p10=None) -> np.ndarray:
     out = np.empty(shots, dtype=np.uint64)
     a = b = None
     if p01 is not None:
         a = np.ascontiguousarray(p01, dtype=np.float64)
         b = np.ascontiguousarray(p10, dtype=np.float64)
-    _check(load().tanq_sample(h, shots, seed, a.ctypes.data_as(_dp) if a is not None else None,
-                              b.ctypes.data_as(_dp) if b is not None else None,
-                              out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))))
+    _check(fn(h, shots, seed, a.ctypes.data_as(_dp) if a is not None else None,
+              b.ctypes.data_as(_dp) if b is not None else None,
+              out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))))
     return out
+
+
+def tanq_sample(h: int, shots: int, seed: int, p01=None, p10=None) -> np.ndarray:
+    return _sample_call(load().tanq_sample, h, shots, seed, p01, p10)
+
+
+def tanq_sample_noalloc(h: int, shots: int, seed: int, p01=None, p10=None) -> np.ndarray:
+    return _sample_call(load().tanq_sample_noalloc, h, shots, seed, p01, p10)
 
 
 def tanq_expect_pauli(h: int, pauli: str) -> float:
