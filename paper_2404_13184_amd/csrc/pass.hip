@@ -93,62 +93,92 @@ __device__ inline T pass_op3m(const T* __restrict__ rb, int r) {
 
 // One superoperator of a pass on the tile in ldsC, by consumer wave cw of NCW, in 3M form:
 // P1 = Sr xr, P2 = Si xi, P3 = (Sr + Si)(xr + xi); Re = P1 - P2, Im = P3 - P1 - P2 -- three
-// real 16 x 16 products per group instead of the real-block form's four.  A wave multiplies its
-// column blocks together, k-step by k-step (independent accumulation chains), and writes only
-// the groups it read, so no barrier inside one superoperator.
+// real 16 x 16 products per group instead of the real-block form's four.  A wave writes only
+// the groups it read, so there is no barrier inside one superoperator.
+//
+// The work is split so that the matrix units of a SIMD stay busy across the barrier that
+// separates superoperators: everything that does not depend on the tile (this lane's operand
+// fragments and the swizzled tile index of its groups' rows) is read into registers while the
+// previous superoperator is still multiplying (PassOps::load), every B operand of the
+// superoperator is read from LDS right after the barrier (all column blocks at once, so the
+// reads wait for nothing but their own latency), and the column blocks are multiplied one
+// after the other, so the additions and LDS writes of one block's results overlap the next
+// block's products.
 template <typename T, int VMAX, int NCW>
-__device__ inline void pass_superop(typename Mfma<T>::c2* ldsC, const T (*opl)[kOp3M],
-                                    const uint16_t (*gxt)[1 << (VMAX - 4)], const PassGeom& g, int j, int cw,
-                                    int lane) {
+struct PassOps {
   using M = Mfma<T>;
   using acc_t = typename M::acc_t;
   using c2 = typename M::c2;
-  constexpr int NB = (1 << (VMAX - 4)) / 16;
-  constexpr int NBW = NB / NCW;
+  static constexpr int G = 1 << (VMAX - 4);  // groups of one superoperator per tile
+  static constexpr int NB = G / 16;          // column blocks (16 groups each)
+  static constexpr int NBW = NB / NCW;       // column blocks per consumer wave
   static_assert(NB % NCW == 0, "every consumer wave gets the same number of column blocks");
-  constexpr int KS = 4;
-  const int kk = lane >> 4;
-  T ar[KS], ai[KS], as[KS];
+  static constexpr int KS = 4;               // k-steps of 4 (16 complex columns)
+  // Raw values read from LDS; nothing is computed from them until apply(), so reading them
+  // never makes the wave wait.  st[l] = S(tile index of local index l); S and the deposit of l
+  // into the tile are both linear over GF(2), so st[a ^ b] = st[a] ^ st[b].
+  T ar[KS], ai[KS], as[KS];  // 3M fragments of this lane (row l % 16, column 4 s + l / 16)
+  uint32_t gx[NBW];          // S(group part) of this lane's group in each of its column blocks
+  uint32_t skk;              // st[kk], kk = lane / 16: this lane's B row within a k-step
+  uint32_t srow;             // st[4 kk]: output row 4 kk of an FP32 accumulator (unused for FP64)
+  u32x4 stk;                 // st[0], st[4], st[8], st[12]: the k-step row offsets
+  u32x4 st0;                 // st[0..3]: FP32 accumulator rows 4 kk + r (unused for FP64)
+
+  // stl: the superoperator's 16 offsets st[l] followed by st[0], st[4], st[8], st[12]
+  __device__ inline void load(const T* __restrict__ op, const uint16_t* __restrict__ gxt, const uint32_t* stl, int cw,
+                              int lane) {
+    const int kk = lane >> 4;
 #pragma unroll
-  for (int s = 0; s < KS; ++s) {
-    ar[s] = opl[j][(s * 3 + 0) * 64 + lane];
-    ai[s] = opl[j][(s * 3 + 1) * 64 + lane];
-    as[s] = opl[j][(s * 3 + 2) * 64 + lane];
-  }
-  const uint32_t* st = g.stj[j];
-  const uint32_t skk = ((kk & 1) ? st[1] : 0u) ^ ((kk & 2) ? st[2] : 0u);  // S(tile index of row kk)
-  uint32_t gx[NBW];
-  acc_t p1[NBW], p2[NBW], p3[NBW];
+    for (int s = 0; s < KS; ++s) {
+      ar[s] = op[(s * 3 + 0) * 64 + lane];
+      ai[s] = op[(s * 3 + 1) * 64 + lane];
+      as[s] = op[(s * 3 + 2) * 64 + lane];
+    }
 #pragma unroll
-  for (int i = 0; i < NBW; ++i) {
-    gx[i] = gxt[j][(cw + i * NCW) * 16 + (lane & 15)];
-    p1[i] = acc_t{0, 0, 0, 0};
-    p2[i] = acc_t{0, 0, 0, 0};
-    p3[i] = acc_t{0, 0, 0, 0};
-  }
-#pragma unroll
-  for (int s = 0; s < KS; ++s) {
-    c2 v[NBW];
-#pragma unroll
-    for (int i = 0; i < NBW; ++i) v[i] = ldsC[(st[4 * s] ^ skk) ^ gx[i]];
-#pragma unroll
-    for (int i = 0; i < NBW; ++i) {
-      const T br = v[i][0], bi = v[i][1];
-      p1[i] = M::mma(ar[s], br, p1[i]);
-      p2[i] = M::mma(ai[s], bi, p2[i]);
-      p3[i] = M::mma(as[s], br + bi, p3[i]);
+    for (int i = 0; i < NBW; ++i) gx[i] = gxt[(cw + i * NCW) * 16 + (lane & 15)];
+    skk = stl[kk];
+    stk = *reinterpret_cast<const u32x4*>(stl + 16);
+    if constexpr (!M::kRowsStrided) {
+      srow = stl[4 * kk];
+      st0 = *reinterpret_cast<const u32x4*>(stl);
     }
   }
-  // output row of accumulator value r: kk + 4 r (FP64) or 4 kk + r (FP32)
-  const uint32_t srow = M::kRowsStrided ? skk : (((kk & 1) ? st[4] : 0u) ^ ((kk & 2) ? st[8] : 0u));
+
+  // B operands of every column block of this wave (issued right after the barrier)
+  __device__ inline void read(const c2* ldsC, c2 (&v)[NBW][KS]) const {
 #pragma unroll
-  for (int i = 0; i < NBW; ++i)
+    for (int i = 0; i < NBW; ++i)
+#pragma unroll
+      for (int s = 0; s < KS; ++s) v[i][s] = ldsC[(stk[s] ^ skk) ^ gx[i]];
+  }
+
+  struct Acc {
+    acc_t p1, p2, p3;
+  };
+
+  // the three real products of column block i
+  __device__ inline Acc products(const c2 (&v)[NBW][KS], int i) const {
+    Acc a{acc_t{0, 0, 0, 0}, acc_t{0, 0, 0, 0}, acc_t{0, 0, 0, 0}};
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      const T br = v[i][s][0], bi = v[i][s][1];
+      a.p1 = M::mma(ar[s], br, a.p1);
+      a.p2 = M::mma(ai[s], bi, a.p2);
+      a.p3 = M::mma(as[s], br + bi, a.p3);
+    }
+    return a;
+  }
+
+  // the 3M combination of block i written back in place; accumulator value r holds output row
+  // kk + 4 r (FP64) or 4 kk + r (FP32)
+  __device__ inline void write(c2* ldsC, const Acc& a, int i) const {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const uint32_t e = (srow ^ (M::kRowsStrided ? st[4 * r] : st[r])) ^ gx[i];
-      ldsC[e] = c2{p1[i][r] - p2[i][r], p3[i][r] - p1[i][r] - p2[i][r]};
+      const uint32_t e = M::kRowsStrided ? ((stk[r] ^ skk) ^ gx[i]) : ((st0[r] ^ srow) ^ gx[i]);
+      ldsC[e] = c2{a.p1[r] - a.p2[r], a.p3[r] - a.p1[r] - a.p2[r]};
     }
-}
+  }
+};
 
 // Producer: stream one tile into buf with direct global-to-LDS loads (lane data lands at the
 // wave's base + 16 * lane, so slot it * PT + tid receives the 16 bytes at offset off[it]).
@@ -177,6 +207,10 @@ __global__ __launch_bounds__(NT) void apply_pass_ws_kernel(T* __restrict__ rho, 
   __shared__ u32x4 ldsB[SLOTS];
   __shared__ T opl[MMAX][kOp3M];
   __shared__ uint16_t gxt[MMAX][G];
+  // st[l] of every superoperator (16 words), then st[0], st[4], st[8], st[12]
+  __shared__ __align__(16) uint32_t stl[MMAX][20];
+  // global offset of the part it * CT of a consumer's store slot index, it < CITERS
+  __shared__ uint64_t soff[CITERS];
   // base offset of the tile in each buffer, written by the producer with its loads: the
   // consumers take it from LDS rather than recomputing it from the run table (which the
   // compiler may read with vector loads, and waiting for those would wait for the stores)
@@ -190,6 +224,11 @@ __global__ __launch_bounds__(NT) void apply_pass_ws_kernel(T* __restrict__ rho, 
   if (tile >= g.ntiles) return;  // uniform per workgroup
   for (int idx = tid; idx < g.m * kOp3M; idx += NT)
     opl[idx / kOp3M][idx % kOp3M] = pass_op3m<T>(frags + g.op_off[idx / kOp3M], idx % kOp3M);
+  if (tid < CITERS) soff[tid] = pass_slot_off<T, VMAX>((uint32_t)(tid * CT * EPS), g);
+  for (int idx = tid; idx < g.m * 20; idx += NT) {
+    const int j = idx / 20, l = idx % 20;
+    stl[j][l] = g.stj[j][l < 16 ? l : 4 * (l - 16)];
+  }
   for (int idx = tid; idx < g.m * G; idx += NT) {
     const int j = idx / G, gi = idx % G;
     gxt[j][gi] = (uint16_t)pass_swz<T>(pdep32((uint32_t)gi, g.free_mask[j]), g);
@@ -225,23 +264,57 @@ __global__ __launch_bounds__(NT) void apply_pass_ws_kernel(T* __restrict__ rho, 
     }
   } else {
     // ---------------- consumers ----------------
+    using Ops = PassOps<T, VMAX, NCW>;
+    using c2 = typename Mfma<T>::c2;
     const int cw = wave - NPW;  // consumer wave 0..NCW-1
     const int ct = tid - PT;    // consumer thread 0..CT-1
-    uint64_t off[CITERS];
-#pragma unroll
-    for (int it = 0; it < CITERS; ++it) off[it] = pass_slot_off<T, VMAX>((uint32_t)((it * CT + ct) * EPS), g);
+    // global offset of the slots this thread stores: the slot index it * CT + ct splits into
+    // disjoint bit fields and the offset is linear in them over GF(2) (swizzle and bit deposit
+    // are), so offset = offset(ct part) ^ offset(it part), the latter the same for every thread
+    const uint64_t off_ct = pass_slot_off<T, VMAX>((uint32_t)(ct * EPS), g);
+    // two operand sets: superoperator j multiplies with ops[j & 1] while ops[(j + 1) & 1] is
+    // filled for j + 1 (for superoperator 0 of the next tile after the last one)
+    Ops ops[2];
+    ops[0].load(opl[0], gxt[0], stl[0], cw, lane);
     raw_barrier();  // B0: first tile ready
     for (int t = 0;; ++t) {
       const uint64_t cur = tbase[t & 1];
       const uint64_t next = tile + gridDim.x;
       const bool more = next < g.ntiles;
       u32x4* buf = (t & 1) ? ldsB : ldsA;
-      for (int j = 0; j < g.m; ++j) {
-        pass_superop<T, VMAX, NCW>(reinterpret_cast<typename Mfma<T>::c2*>(buf), opl, gxt, g, j, cw, lane);
+      c2* bufC = reinterpret_cast<c2*>(buf);
+#pragma unroll
+      for (int j = 0; j < MMAX; ++j) {
+        if (j >= g.m) break;  // uniform
+        c2 v[Ops::NBW][Ops::KS];
+        typename Ops::Acc acc[2];
+        const Ops& o = ops[j & 1];
+        o.read(bufC, v);
+        // LDS returns in order: the first column block's products are issued before the next
+        // operands are requested (unconditionally, so the waits can count them: after the last
+        // superoperator, superoperator 0 of the next tile), so they wait only for their B reads
+        __builtin_amdgcn_sched_barrier(0);
+        acc[0] = o.products(v, 0);
+        __builtin_amdgcn_sched_barrier(0);
+        {
+          const int jn = (j + 1 < g.m) ? j + 1 : 0;
+          ops[(j + 1) & 1].load(opl[jn], gxt[jn], stl[jn], cw, lane);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        // block i's products, then block i - 1's results: the additions and LDS writes of one
+        // block run while the matrix units work on the next
+#pragma unroll
+        for (int i = 1; i < Ops::NBW; ++i) {
+          acc[i & 1] = o.products(v, i);
+          o.write(bufC, acc[(i - 1) & 1], i - 1);
+        }
+        o.write(bufC, acc[(Ops::NBW - 1) & 1], Ops::NBW - 1);
         raw_barrier();  // the next superoperator (or the store) reads what other waves wrote
       }
+      if (g.m & 1) ops[0] = ops[1];  // the last superoperator left superoperator 0 in ops[m & 1]
 #pragma unroll
-      for (int it = 0; it < CITERS; ++it) *reinterpret_cast<u32x4*>(rho + 2 * (cur + off[it])) = buf[it * CT + ct];
+      for (int it = 0; it < CITERS; ++it)
+        *reinterpret_cast<u32x4*>(rho + 2 * (cur + (off_ct ^ soff[it]))) = buf[it * CT + ct];
       raw_barrier();  // B_free: this buffer is read out
       if (!more) break;
       raw_barrier();  // B0: next tile ready
