@@ -454,6 +454,8 @@ def serve_batched(T, W, reqs, arrays, prec, width, budget, slots, steps, cohort_
     out = _latency_summary(lat, len(lat), reqs[0].arrival_s, last)
     out.update({"peak_device_bytes": int(st["peak_bytes"]), "budget_bytes": int(st["budget_bytes"]),
                 "batched_applies": int(st["steps"]), "graph_launches": int(st["launches"]),
+                "tile_applies": int(st["tiles"]), "chunks": int(st["chunks"]),
+                "avg_chunk_tiles": round(st["tiles"] / max(1, st["chunks"]), 2),
                 "wall_s": round(time.perf_counter() - t0, 2)})
     return out
 

@@ -416,6 +416,9 @@ typedef struct {
   size_t bytes_in_use, peak_bytes, budget_bytes;
   int active, pending;
   double clock;          /* seconds since creation */
+  uint64_t tiles;        /* tile multiplications of the batched launches so far (one tile of one
+                            state by one fused superoperator) */
+  uint64_t chunks;       /* work-list chunks those launches claimed */
 } tanq_server_stats;
 
 /* Create a server on the current device with its own stream and scheduler thread.

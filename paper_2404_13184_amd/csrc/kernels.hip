@@ -49,25 +49,31 @@ __global__ void fill_random_kernel(T* __restrict__ rho, uint64_t nel, uint64_t s
 }
 
 // rho <- f rho in place: every element read once and written once with 16-byte accesses
-// (one FP64 or two FP32 complex values per access).  Each thread loads U accesses spaced one
-// workgroup apart before it stores any of them, so a wave keeps U loads in flight; the grid
-// strides over the state.  This is the plain streaming kernel of the state buffer (one read
-// and one write of every element, nothing else), so its rate is the bandwidth that any
-// in-place pass over vec(rho) can reach.
+// (one FP64 or two FP32 complex values per access), non-temporal (the data is not reused).
+// Each workgroup owns one contiguous range of the state; the ranges of the workgroups that run
+// on one XCD (workgroups are dealt round-robin over the 8 XCDs) are adjacent.  Each thread
+// loads U accesses spaced one workgroup apart before it stores any of them, so a wave keeps U
+// loads in flight.  This is the plain streaming kernel of the state buffer (one read and one
+// write of every element, nothing else), so its rate is the bandwidth that an in-place pass
+// over vec(rho) can reach.
 template <typename V, typename S, int U>
 __global__ __launch_bounds__(256) void scale_kernel(V* __restrict__ x, uint64_t nvec, S f) {
-  const uint64_t stride = (uint64_t)gridDim.x * (256 * U);
-  for (uint64_t base = (uint64_t)blockIdx.x * (256 * U) + threadIdx.x; base < nvec; base += stride) {
+  const uint32_t G = gridDim.x, b = blockIdx.x;
+  const uint32_t r = (G % 8u == 0u) ? (b % 8u) * (G / 8u) + b / 8u : b;  // a bijection of [0, G)
+  const uint64_t per = (nvec + G - 1) / G;
+  const uint64_t lo = (uint64_t)r * per;
+  const uint64_t hi = lo + per < nvec ? lo + per : nvec;
+  for (uint64_t base = lo + threadIdx.x; base < hi; base += 256 * U) {
     V v[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const uint64_t i = base + (uint64_t)u * 256;
-      if (i < nvec) v[u] = x[i];
+      if (i < hi) v[u] = __builtin_nontemporal_load(x + i);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const uint64_t i = base + (uint64_t)u * 256;
-      if (i < nvec) x[i] = v[u] * f;
+      if (i < hi) __builtin_nontemporal_store(v[u] * f, x + i);
     }
   }
 }
@@ -477,7 +483,7 @@ void launch_scale(void* rho, int n, tanq_prec p, double f, hipStream_t s) {
   // 16-byte accesses: one FP64 complex element, or two FP32 ones
   const uint64_t nvec = (p == TANQ_F64) ? (1ull << (2 * n)) : (1ull << (2 * n)) / 2;
   uint64_t blocks = (nvec + 256 * U - 1) / (256 * U);
-  const uint64_t cap = (uint64_t)device_cu_count() * 16;
+  const uint64_t cap = (uint64_t)device_cu_count() * 32;
   if (blocks > cap) blocks = cap;
   if (p == TANQ_F64)
     hipLaunchKernelGGL((scale_kernel<f64x2, double, U>), dim3((unsigned)blocks), dim3(256), 0, s, (f64x2*)rho,

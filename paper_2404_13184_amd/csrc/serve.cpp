@@ -188,6 +188,7 @@ struct tanq_server_s {
 
   // statistics (written by the scheduler, read by tanq_server_stats_get)
   std::atomic<uint64_t> n_submitted{0}, n_admitted{0}, n_completed{0}, n_rejected{0}, n_launches{0}, n_steps{0};
+  std::atomic<uint64_t> n_tiles{0}, n_chunks{0};
   std::atomic<size_t> bytes_in_use{0}, peak_bytes{0};
   std::atomic<int> n_active{0};
 
@@ -377,6 +378,8 @@ void tanq_server_s::run_iteration() {
     }
     step_count(W, s)[0] = nc;
     step_count(W, s)[1] = 0;  // next unclaimed chunk, reset by the copy before each launch
+    for (uint32_t i = 0; i < ni; ++i) n_tiles += ntiles[i];
+    n_chunks += nc;
     if (nc) ++n_steps;
   }
   if (graph[b]) {
@@ -776,6 +779,8 @@ tanq_status tanq_server_stats_get(tanq_server s, tanq_server_stats* out) {
     out->active = s->n_active.load();
     out->pending = (int)s->pending.size();
     out->clock = s->now();
+    out->tiles = s->n_tiles;
+    out->chunks = s->n_chunks;
   });
 }
 

@@ -85,7 +85,8 @@ class ServerStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_uint64), ("admitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
                 ("rejected", ctypes.c_uint64), ("launches", ctypes.c_uint64), ("steps", ctypes.c_uint64),
                 ("bytes_in_use", ctypes.c_size_t), ("peak_bytes", ctypes.c_size_t), ("budget_bytes", ctypes.c_size_t),
-                ("active", ctypes.c_int), ("pending", ctypes.c_int), ("clock", ctypes.c_double)]
+                ("active", ctypes.c_int), ("pending", ctypes.c_int), ("clock", ctypes.c_double),
+                ("tiles", ctypes.c_uint64), ("chunks", ctypes.c_uint64)]
 
 
 class FusedInfo(ctypes.Structure):
