@@ -45,6 +45,8 @@ typedef int tanq_status;
 #define TANQ_E_STATE (-4)       /* handle in the wrong state (e.g. mismatched precision) */
 #define TANQ_E_UNSUPPORTED (-5) /* valid request that this build does not implement */
 #define TANQ_E_AGAIN (-6)       /* server: result not ready yet */
+#define TANQ_E_CANCELED (-7)    /* server: the request was cancelled (tanq_server_cancel) */
+#define TANQ_E_TIMEOUT (-8)     /* server: the request did not finish within the server's timeout */
 
 typedef enum { TANQ_F64 = 0, TANQ_F32 = 1 } tanq_prec;
 
@@ -390,6 +392,10 @@ typedef struct {
                            whose states total at most cohort_bytes (at least one request), so
                            that the iteration's consecutive passes over those states can hit the
                            device's last-level cache */
+  double request_timeout_s; /* > 0: a request not finished this many seconds after its submission
+                               is dropped with status TANQ_E_TIMEOUT (queued: taken off the queue;
+                               resident: no further batched applies, its slot and memory freed
+                               once the launches already queued for it have run); 0: no timeout */
 } tanq_server_config;
 
 typedef struct {
@@ -410,7 +416,7 @@ typedef struct {
 } tanq_result;
 
 typedef struct {
-  uint64_t submitted, admitted, completed, rejected;
+  uint64_t submitted, admitted, completed, rejected; /* completed: finished with outputs */
   uint64_t launches;     /* scheduler iterations (each steps_per_launch batched applies) */
   uint64_t steps;        /* batched applies that had work */
   size_t bytes_in_use, peak_bytes, budget_bytes;
@@ -419,6 +425,7 @@ typedef struct {
   uint64_t tiles;        /* tile multiplications of the batched launches so far (one tile of one
                             state by one fused superoperator) */
   uint64_t chunks;       /* work-list chunks those launches claimed */
+  uint64_t dropped;      /* requests cancelled or timed out */
 } tanq_server_stats;
 
 /* Create a server on the current device with its own stream and scheduler thread.
@@ -430,6 +437,13 @@ tanq_status tanq_server_create(const tanq_server_config* cfg, tanq_server* out);
  * outside [width, 14]; TANQ_E_OOM if the request alone exceeds the budget (it could never be
  * admitted).  A circuit with no operations completes with the outputs of |0..0><0..0|. */
 tanq_status tanq_server_submit(tanq_server s, tanq_circuit c, const tanq_outputs* outs, uint64_t* ticket);
+
+/* Cancel a request.  A queued request leaves the queue at once; a resident one gets no further
+ * batched applies and frees its slot and device memory once the launches already queued for it
+ * have run.  Its result then has status TANQ_E_CANCELED and no outputs.  A request that has
+ * already finished keeps its result (TANQ_OK, nothing changes).  TANQ_E_ARG for an unknown
+ * ticket.  Never blocks on the GPU. */
+tanq_status tanq_server_cancel(tanq_server s, uint64_t ticket);
 
 /* Result of a finished request (TANQ_E_AGAIN while it is not finished); wait blocks. */
 tanq_status tanq_server_poll(tanq_server s, uint64_t ticket, tanq_result* out);

@@ -55,6 +55,51 @@ __device__ inline void batch_tiles(T* __restrict__ rho, const IO& io, const Op& 
   }
 }
 
+// k = 3: the tiles [t0, t1) of one item with two LDS buffers.  Each tile is multiplied out of
+// place from `in` into `out` (every wave reads the whole tile, so in place would need a barrier
+// between the reads and the writes); one barrier then separates the multiplication from the
+// store of `out` and the refill of `in` with the next tile (prefetched into registers), and a
+// second one the refill from the next multiplication.
+template <bool FULL, typename T, typename IO, typename Op, typename G>
+__device__ inline void batch_tiles_oop(T* __restrict__ rho, const IO& io, const Op& op, const G& g, u32x4* in,
+                                       u32x4* out, uint32_t t0, uint32_t t1, int tid, int lane, int wave) {
+  using c2 = typename Mfma<T>::c2;
+  uint64_t cur = tile_base(g, t0);
+  u32x4 buf[IO::ITERS];
+#pragma unroll
+  for (int it = 0; it < IO::ITERS; ++it)
+    if (io.template has<FULL>(it, tid)) buf[it] = *reinterpret_cast<const u32x4*>(rho + 2 * (cur + io.off[it]));
+#pragma unroll
+  for (int it = 0; it < IO::ITERS; ++it)
+    if (io.template has<FULL>(it, tid)) in[io.lslot[it]] = buf[it];
+  lds_barrier();
+  for (uint32_t t = t0;;) {
+    const bool more = t + 1 < t1;
+    uint64_t nbase = 0;
+    if (more) {
+      nbase = tile_base(g, t + 1);
+#pragma unroll
+      for (int it = 0; it < IO::ITERS; ++it)
+        if (io.template has<FULL>(it, tid))
+          buf[it] = *reinterpret_cast<const u32x4*>(rho + 2 * (nbase + io.off[it]));
+    }
+    op.template compute_to<FULL>(reinterpret_cast<const c2*>(in), reinterpret_cast<c2*>(out), g, lane, wave);
+    lds_barrier();  // results complete; `in` is no longer read
+#pragma unroll
+    for (int it = 0; it < IO::ITERS; ++it)
+      if (io.template has<FULL>(it, tid)) *reinterpret_cast<u32x4*>(rho + 2 * (cur + io.off[it])) = out[io.lslot[it]];
+    if (more) {
+#pragma unroll
+      for (int it = 0; it < IO::ITERS; ++it)
+        if (io.template has<FULL>(it, tid)) in[io.lslot[it]] = buf[it];
+    }
+    lds_barrier();  // `out` read out and `in` refilled (or, after the last tile, free for the next chunk)
+    if (!more) break;
+    ++t;
+    cur = nbase;
+  }
+}
+
 template <typename T, int K, int VMAX, int NT>
 __global__ __launch_bounds__(NT) void batch_apply_kernel(const BatchItem* __restrict__ items,
                                                          const BatchChunk* __restrict__ chunks,
@@ -64,6 +109,10 @@ __global__ __launch_bounds__(NT) void batch_apply_kernel(const BatchItem* __rest
   static_assert(sizeof(ApplyGeom) % 4 == 0, "geometry copied as dwords");
 
   __shared__ u32x4 lds[IO::SLOTS];
+  // FP32 k = 3: the out-of-place result buffer (FP64 k = 3 stays in place: its operand slices
+  // leave no registers for the second path)
+  constexpr bool kOop = K == 3 && std::is_same_v<T, float>;
+  __shared__ u32x4 lds2[kOop ? IO::SLOTS : 1];
   __shared__ ApplyGeom sg;
 
   const int tid = threadIdx.x;
@@ -104,10 +153,17 @@ __global__ __launch_bounds__(NT) void batch_apply_kernel(const BatchItem* __rest
       cur = ch.item;
     }
     if (ch.tile_begin >= ch.tile_end) continue;
-    if (full)
-      batch_tiles<true, T>(rho, io, op, sg, lds, ch.tile_begin, ch.tile_end, tid, lane, wave);
-    else
-      batch_tiles<false, T>(rho, io, op, sg, lds, ch.tile_begin, ch.tile_end, tid, lane, wave);
+    if constexpr (kOop) {
+      if (full)
+        batch_tiles_oop<true, T>(rho, io, op, sg, lds, lds2, ch.tile_begin, ch.tile_end, tid, lane, wave);
+      else
+        batch_tiles_oop<false, T>(rho, io, op, sg, lds, lds2, ch.tile_begin, ch.tile_end, tid, lane, wave);
+    } else {
+      if (full)
+        batch_tiles<true, T>(rho, io, op, sg, lds, ch.tile_begin, ch.tile_end, tid, lane, wave);
+      else
+        batch_tiles<false, T>(rho, io, op, sg, lds, ch.tile_begin, ch.tile_end, tid, lane, wave);
+    }
   }
 }
 

@@ -105,6 +105,9 @@ struct ServeRequest {
   std::vector<ApplyGeom> geom;   // per fused block
   size_t cursor = 0;
   bool finishing = false;  // its reductions are queued; leaves the resident set
+  tanq_status drop = TANQ_OK;  // TANQ_E_CANCELED / TANQ_E_TIMEOUT: stop and free it, no outputs
+  bool outputs_queued = false; // its reductions were queued (a later cancel no longer applies)
+  double deadline = 0;         // server clock time after which it times out (0: none)
   FuseLayout layout;  // planned at submit (exact footprint); consumed at admission
   // results
   double trace = 0.0;
@@ -188,7 +191,7 @@ struct tanq_server_s {
 
   // statistics (written by the scheduler, read by tanq_server_stats_get)
   std::atomic<uint64_t> n_submitted{0}, n_admitted{0}, n_completed{0}, n_rejected{0}, n_launches{0}, n_steps{0};
-  std::atomic<uint64_t> n_tiles{0}, n_chunks{0};
+  std::atomic<uint64_t> n_tiles{0}, n_chunks{0}, n_dropped{0};
   std::atomic<size_t> bytes_in_use{0}, peak_bytes{0};
   std::atomic<int> n_active{0};
 
@@ -320,6 +323,22 @@ void tanq_server_s::run_iteration() {
     }
     rr_next = (rr_next + cohort.size()) % active.size();
   }
+  // dropped requests (cancelled or timed out) leave now: no further applies, no outputs; the
+  // event recorded after this iteration's launches orders the release of their memory after
+  // every launch already queued for them
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    const double t = now();
+    for (ServeRequest* r : active)
+      if (!r->finishing && r->drop == TANQ_OK && r->deadline > 0 && t > r->deadline) r->drop = TANQ_E_TIMEOUT;
+    for (ServeRequest* r : active)
+      if (!r->finishing && r->drop != TANQ_OK) {
+        r->finishing = true;
+        done_now.push_back(r);
+      }
+  }
+  cohort.erase(std::remove_if(cohort.begin(), cohort.end(), [](ServeRequest* r) { return r->finishing; }),
+               cohort.end());
   // a circuit with no operations has nothing to apply: its outputs are those of |0..0><0..0|
   for (ServeRequest* r : cohort)
     if (r->geom.empty() && !r->finishing) {
@@ -394,6 +413,11 @@ void tanq_server_s::run_iteration() {
   if (!done_now.empty()) {
     const tanq_prec p = (tanq_prec)cfg.prec;
     for (ServeRequest* r : done_now) {
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        if (r->drop != TANQ_OK) continue;  // no outputs
+        r->outputs_queued = true;
+      }
       unsigned char* rho = arena_base + r->rho_off;
       double* hres = (double*)(pinned_base + r->res_off);
       launch_diag(rho, r->n, p, probs_dev, partials, result_dev, 1, stream);
@@ -441,22 +465,30 @@ void tanq_server_s::finalize_done(bool block) {
     {
       std::lock_guard<std::mutex> lk(mu);
       for (ServeRequest* r : f.reqs) {
-        const double* hres = (const double*)(pinned_base + r->res_off);
-        r->trace = hres[0];
-        size_t off = 1;
-        if (r->want_probs) {
-          r->probs.assign(hres + 1, hres + 1 + ((size_t)1 << r->n));
-          off += (size_t)1 << r->n;
+        if (!r->outputs_queued) {
+          r->status = r->drop;
+          r->error = r->drop == TANQ_E_CANCELED ? "request cancelled" : "request timed out";
+        } else {
+          const double* hres = (const double*)(pinned_base + r->res_off);
+          r->trace = hres[0];
+          size_t off = 1;
+          if (r->want_probs) {
+            r->probs.assign(hres + 1, hres + 1 + ((size_t)1 << r->n));
+            off += (size_t)1 << r->n;
+          }
+          r->pauli.resize(r->paulis.size());
+          for (size_t i = 0; i < r->paulis.size(); ++i) r->pauli[i] = hres[off + 2 * i];
         }
-        r->pauli.resize(r->paulis.size());
-        for (size_t i = 0; i < r->paulis.size(); ++i) r->pauli[i] = hres[off + 2 * i];
         arena.release(r->keep_off, r->keep_size);
         pinned.release(r->res_off, r->res_size);
         free_slots.push_back(r->slot);
         r->slot = -1;
         r->t_done = t;
         r->state = 2;
-        ++n_completed;
+        if (!r->outputs_queued)
+          ++n_dropped;
+        else
+          ++n_completed;
       }
     }
     put_event(f.ev);
@@ -476,6 +508,26 @@ void tanq_server_s::loop() {
           if (stop) break;
           cv_submit.wait_for(lk, std::chrono::microseconds(500));
           continue;
+        }
+        // queued requests past their deadline leave the queue
+        if (cfg.request_timeout_s > 0 && !pending.empty()) {
+          const double t = now();
+          bool any = false;
+          for (auto it = pending.begin(); it != pending.end();) {
+            ServeRequest* r = *it;
+            if (r->deadline > 0 && t > r->deadline) {
+              r->status = TANQ_E_TIMEOUT;
+              r->error = "request timed out";
+              r->t_done = t;
+              r->state = 2;
+              ++n_dropped;
+              it = pending.erase(it);
+              any = true;
+            } else {
+              ++it;
+            }
+          }
+          if (any) cv_done.notify_all();
         }
         // FIFO admission by slot and footprint (head-of-line: a request that does not fit
         // waits for memory instead of being overtaken)
@@ -618,6 +670,7 @@ tanq_status tanq_server_create(const tanq_server_config* cfg, tanq_server* out) 
     if (c.width != 2 && c.width != 3) fail(TANQ_E_ARG, "width must be 0, 2 or 3");
     if (c.steps_per_launch < 1 || c.steps_per_launch > 64) fail(TANQ_E_ARG, "steps_per_launch must be 1..64");
     if (c.hbm_budget < (64u << 20)) fail(TANQ_E_ARG, "hbm_budget must be at least 64 MiB");
+    if (!(c.request_timeout_s >= 0.0)) fail(TANQ_E_ARG, "request_timeout_s must be >= 0");
     size_t free_b = 0, total_b = 0;
     TANQ_HIP(hipMemGetInfo(&free_b, &total_b));
     if (c.hbm_budget + (256ull << 20) > free_b) fail(TANQ_E_OOM, "hbm_budget exceeds free device memory");
@@ -703,6 +756,7 @@ tanq_status tanq_server_submit(tanq_server s, tanq_circuit c, const tanq_outputs
     }
     r->ticket = s->next_ticket++;
     r->t_submit = s->now();
+    if (s->cfg.request_timeout_s > 0) r->deadline = r->t_submit + s->cfg.request_timeout_s;
     *ticket = r->ticket;
     s->pending.push_back(r.get());
     s->all[r->ticket] = std::move(r);
@@ -752,6 +806,33 @@ tanq_status tanq_server_wait(tanq_server s, uint64_t ticket, tanq_result* out) {
   });
 }
 
+tanq_status tanq_server_cancel(tanq_server s, uint64_t ticket) {
+  return guarded([&] {
+    if (!s) fail(TANQ_E_ARG, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->all.find(ticket);
+    if (it == s->all.end()) fail(TANQ_E_ARG, "unknown ticket");
+    ServeRequest* r = it->second.get();
+    if (r->state == 2) return;  // finished: the result stands
+    if (r->state == 0) {
+      // still queued: leave the queue now
+      auto q = std::find(s->pending.begin(), s->pending.end(), r);
+      if (q != s->pending.end()) {
+        s->pending.erase(q);
+        r->status = TANQ_E_CANCELED;
+        r->error = "request cancelled";
+        r->t_done = s->now();
+        r->state = 2;
+        ++s->n_dropped;
+        s->cv_done.notify_all();
+        return;
+      }
+    }
+    // admitted (or being admitted): the scheduler drops it at its next iteration
+    if (r->drop == TANQ_OK) r->drop = TANQ_E_CANCELED;
+  });
+}
+
 tanq_status tanq_server_release(tanq_server s, uint64_t ticket) {
   return guarded([&] {
     if (!s) fail(TANQ_E_ARG, "NULL argument");
@@ -781,6 +862,7 @@ tanq_status tanq_server_stats_get(tanq_server s, tanq_server_stats* out) {
     out->clock = s->now();
     out->tiles = s->n_tiles;
     out->chunks = s->n_chunks;
+    out->dropped = s->n_dropped;
   });
 }
 

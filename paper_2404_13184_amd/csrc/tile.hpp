@@ -328,6 +328,36 @@ struct Op3 {
     }
   }
 
+  // Out of place: reads the tile from `in`, writes the results to `out` (the same layout), so no
+  // barrier is needed between the reads and the writes.
+  template <bool FULL, typename G>
+  __device__ inline void compute_to(const c2* in, c2* out, const G& g, int lane, int wave) const {
+    const int part = wave >> 2;
+#pragma unroll
+    for (int i = 0; i < NBW; ++i) {
+      if (!(FULL || part + i * NPART < nblk)) continue;
+      acc_t p1 = acc_t{0, 0, 0, 0}, p2 = acc_t{0, 0, 0, 0}, p3 = acc_t{0, 0, 0, 0};
+      // inactive lanes (partial tiles only) read group 0, which is in the tile, and write nothing
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        const uint32_t e = ((g.tj[4 * s] + tjk) ^ xg[i]) + gj[i];
+        const c2 v = in[e];
+        const T br = v[0], bi = v[1];
+        p1 = M::mma(ar[s], br, p1);
+        p2 = M::mma(ai[s], bi, p2);
+        p3 = M::mma(as[s], br + bi, p3);
+      }
+      if (FULL || act[i]) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const uint32_t trow = trow0 + (M::kRowsStrided ? g.tj[4 * r] : g.tj[r]);
+          const uint32_t e = ((tjm + trow) ^ xg[i]) + gj[i];
+          out[e] = c2{p1[r] - p2[r], p3[r] - p1[r] - p2[r]};
+        }
+      }
+    }
+  }
+
   template <bool FULL, bool RAW = false, typename G>
   __device__ inline void compute(c2* ldsC, const G& g, int lane, int wave) const {
     const int part = wave >> 2;

@@ -23,6 +23,8 @@ TANQ_E_HIP = -3
 TANQ_E_STATE = -4
 TANQ_E_UNSUPPORTED = -5
 TANQ_E_AGAIN = -6
+TANQ_E_CANCELED = -7
+TANQ_E_TIMEOUT = -8
 
 TANQ_F64 = 0
 TANQ_F32 = 1
@@ -48,7 +50,7 @@ EXPORTED = [
     "tanq_process_chi_1q",
     "tanq_expect_pauli", "tanq_expect_pauli_c", "tanq_expect_pauli_batch",
     "tanq_dm_compare",
-    "tanq_server_create", "tanq_server_submit", "tanq_server_poll", "tanq_server_wait", "tanq_server_release",
+    "tanq_server_create", "tanq_server_submit", "tanq_server_poll", "tanq_server_wait", "tanq_server_release", "tanq_server_cancel",
     "tanq_server_stats_get", "tanq_server_destroy",
 ]
 
@@ -67,7 +69,7 @@ class Variant(ctypes.Structure):
 class ServerConfig(ctypes.Structure):
     _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_slots", ctypes.c_int), ("prec", ctypes.c_int),
                 ("width", ctypes.c_int), ("steps_per_launch", ctypes.c_int), ("use_graphs", ctypes.c_int),
-                ("cohort_bytes", ctypes.c_size_t)]
+                ("cohort_bytes", ctypes.c_size_t), ("request_timeout_s", ctypes.c_double)]
 
 
 class Outputs(ctypes.Structure):
@@ -86,7 +88,7 @@ class ServerStats(ctypes.Structure):
                 ("rejected", ctypes.c_uint64), ("launches", ctypes.c_uint64), ("steps", ctypes.c_uint64),
                 ("bytes_in_use", ctypes.c_size_t), ("peak_bytes", ctypes.c_size_t), ("budget_bytes", ctypes.c_size_t),
                 ("active", ctypes.c_int), ("pending", ctypes.c_int), ("clock", ctypes.c_double),
-                ("tiles", ctypes.c_uint64), ("chunks", ctypes.c_uint64)]
+                ("tiles", ctypes.c_uint64), ("chunks", ctypes.c_uint64), ("dropped", ctypes.c_uint64)]
 
 
 class FusedInfo(ctypes.Structure):
@@ -161,6 +163,7 @@ _SIGS = {
     "tanq_server_poll": ([_vp, ctypes.c_uint64, ctypes.POINTER(Result)], ctypes.c_int),
     "tanq_server_wait": ([_vp, ctypes.c_uint64, ctypes.POINTER(Result)], ctypes.c_int),
     "tanq_server_release": ([_vp, ctypes.c_uint64], ctypes.c_int),
+    "tanq_server_cancel": ([_vp, ctypes.c_uint64], ctypes.c_int),
     "tanq_server_stats_get": ([_vp, ctypes.POINTER(ServerStats)], ctypes.c_int),
     "tanq_server_destroy": ([_vp], ctypes.c_int),
 }
@@ -539,9 +542,10 @@ def tanq_dm_compare(a: int, b: int):
 
 
 def tanq_server_create(hbm_budget: int, max_slots: int, prec: int, width: int = 2,
-                       steps_per_launch: int = 8, use_graphs: bool = True, cohort_bytes: int = 0) -> int:
+                       steps_per_launch: int = 8, use_graphs: bool = True, cohort_bytes: int = 0,
+                       request_timeout_s: float = 0.0) -> int:
     cfg = ServerConfig(hbm_budget, max_slots, prec, width, steps_per_launch, int(bool(use_graphs)),
-                       int(cohort_bytes))
+                       int(cohort_bytes), float(request_timeout_s))
     h = _vp()
     _check(load().tanq_server_create(ctypes.byref(cfg), ctypes.byref(h)))
     return h.value
@@ -584,6 +588,10 @@ def tanq_server_wait(h: int, ticket: int) -> dict:
 
 def tanq_server_release(h: int, ticket: int):
     _check(load().tanq_server_release(h, ticket))
+
+
+def tanq_server_cancel(h: int, ticket: int):
+    _check(load().tanq_server_cancel(h, ticket))
 
 
 def tanq_server_stats_get(h: int) -> dict:
@@ -796,9 +804,10 @@ class Server:
     """Continuous-batching server (see tanq_server_* in include/tanq.h)."""
 
     def __init__(self, hbm_budget: int, max_slots: int = 64, prec="f32", width: int = 2,
-                 steps_per_launch: int = 8, use_graphs: bool = True, cohort_bytes: int = 0):
+                 steps_per_launch: int = 8, use_graphs: bool = True, cohort_bytes: int = 0,
+                 request_timeout_s: float = 0.0):
         self.h = tanq_server_create(hbm_budget, max_slots, _prec(prec), width, steps_per_launch, use_graphs,
-                                    cohort_bytes)
+                                    cohort_bytes, request_timeout_s)
 
     def submit(self, n: int, ops: Iterable = (), probs: bool = True, paulis: Sequence[str] = (), arrays=None) -> int:
         c = Circuit(n, ops, arrays=arrays)
@@ -815,6 +824,9 @@ class Server:
 
     def release(self, ticket: int):
         tanq_server_release(self.h, ticket)
+
+    def cancel(self, ticket: int):
+        tanq_server_cancel(self.h, ticket)
 
     def stats(self) -> dict:
         return tanq_server_stats_get(self.h)

@@ -297,3 +297,9 @@ def test_pass_grouping_on_the_benchmark_circuit(lib):
             assert len(runs) <= most, (prec, len(runs))
     finally:
         c.free()
+
+
+def test_server_cancel_rejects_null(lib):
+    import ctypes
+
+    assert lib.tanq_server_cancel(None, ctypes.c_uint64(1)) == T.TANQ_E_ARG

@@ -150,3 +150,58 @@ def test_request_size_limits():
         for n in (2, 15):  # below the fusion width, above the serving limit
             with pytest.raises(T.TanqError):
                 srv.submit(n, [W.gate(W.hadamard(), (0,))])
+
+
+def test_cancel_queued_and_resident_requests(oracle_mod):
+    """A queued request leaves the queue; a resident one stops and frees its slot and memory;
+    the others finish with correct results; a finished request keeps its result."""
+    heavy = small_requests(2, seed=21, n_range=(12, 12), depth_range=(150, 180))
+    light = small_requests(6, seed=22)
+    say("cancel queued and resident")
+    with T.Server(1024 * MiB, max_slots=1, prec="f64", width=2, steps_per_launch=4) as srv:
+        t_heavy = srv.submit(heavy[0][0], heavy[0][1])  # admitted first (one slot)
+        t_light = [srv.submit(n, ops, probs=True) for n, ops, _ in light]
+        t_queued = srv.submit(heavy[1][0], heavy[1][1])  # behind the others in the queue
+        srv.cancel(t_queued)
+        srv.cancel(t_heavy)
+        r_heavy = srv.wait(t_heavy)
+        r_queued = srv.wait(t_queued)
+        assert r_queued["status"] == T.TANQ_E_CANCELED and r_queued["probs"] is None
+        assert r_queued["t_admit"] == 0.0  # never admitted
+        # the heavy request may have finished before the cancel reached the scheduler; if not,
+        # it is cancelled without outputs
+        assert r_heavy["status"] in (T.TANQ_OK, T.TANQ_E_CANCELED)
+        if r_heavy["status"] == T.TANQ_E_CANCELED:
+            assert r_heavy["probs"] is None
+        for (n, ops, _), t in zip(light, t_light):
+            res = srv.wait(t)
+            assert res["status"] == T.TANQ_OK
+            want = oracle_mod.run(n, ops)
+            p, tr = oracle_mod.diag(want)
+            assert np.abs(res["probs"] - p / tr).max() <= 1e-12
+        done = srv.wait(t_light[0])
+        srv.cancel(t_light[0])  # finished: nothing changes
+        assert srv.wait(t_light[0])["status"] == T.TANQ_OK and np.array_equal(srv.wait(t_light[0])["probs"], done["probs"])
+        with pytest.raises(T.TanqError):
+            srv.cancel(987654321)
+        st = srv.stats()
+        assert st["completed"] + st["dropped"] == len(light) + 2
+        assert st["dropped"] >= 1 and st["bytes_in_use"] == 0 and st["active"] == 0
+
+
+def test_request_timeout():
+    """With a timeout far below a request's run time, requests time out (queued or resident)
+    and free their memory; with a generous one, every request finishes."""
+    reqs = small_requests(6, seed=31, n_range=(11, 12), depth_range=(100, 150))
+    say("request timeout")
+    with T.Server(1024 * MiB, max_slots=2, prec="f32", width=3, steps_per_launch=4,
+                  request_timeout_s=0.002) as srv:
+        tickets = [srv.submit(n, ops) for n, ops, _ in reqs]
+        res = [srv.wait(t) for t in tickets]
+        st = srv.stats()
+    assert all(r["status"] in (T.TANQ_OK, T.TANQ_E_TIMEOUT) for r in res)
+    assert sum(r["status"] == T.TANQ_E_TIMEOUT for r in res) >= len(reqs) - 2
+    assert st["bytes_in_use"] == 0 and st["dropped"] == sum(r["status"] == T.TANQ_E_TIMEOUT for r in res)
+    with T.Server(1024 * MiB, max_slots=2, prec="f32", width=3, steps_per_launch=4, request_timeout_s=600.0) as srv:
+        res = [srv.wait(t) for t in [srv.submit(n, ops) for n, ops, _ in reqs[:3]]]
+    assert all(r["status"] == T.TANQ_OK for r in res)
