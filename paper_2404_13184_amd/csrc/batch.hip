@@ -100,8 +100,17 @@ __device__ inline void batch_tiles_oop(T* __restrict__ rho, const IO& io, const 
   }
 }
 
+// Workgroups per CU the FP32 k = 3 kernel is compiled for: three (at most 168 registers per lane,
+// a few of them spilled outside the multiplication) instead of the two its unconstrained
+// allocation allows; the third workgroup's waves hide the others' barriers and tile turnovers
+// (203 against 198 circuits/s on the serving stream).  Every other shape keeps its allocation.
+template <typename T, int K>
+struct BatchMinBlocks { static constexpr int value = 1; };
+template <>
+struct BatchMinBlocks<float, 3> { static constexpr int value = 3; };
+
 template <typename T, int K, int VMAX, int NT>
-__global__ __launch_bounds__(NT) void batch_apply_kernel(const BatchItem* __restrict__ items,
+__global__ __launch_bounds__(NT, (BatchMinBlocks<T, K>::value)) void batch_apply_kernel(const BatchItem* __restrict__ items,
                                                          const BatchChunk* __restrict__ chunks,
                                                          uint32_t* __restrict__ count) {
   using IO = TileIo<T, VMAX, NT>;
