@@ -189,11 +189,13 @@ def run_precision(T, torch, n, ops, prec, width, steps, warmup):
     circ.free()
     stream_s = time_stream(torch, d, stream)
     log("%s in-place stream over the state: %.3f ms (%.1f GB/s)" % (prec, stream_s * 1e3, d_bytes(d) / stream_s / 1e9))
+    mfma_tf = T.tanq_mfma_rate(prec)
+    log("%s matrix units, multiplication loop alone: %.1f TFLOP/s" % (prec, mfma_tf))
     applies = info["count"] * steps
     return {"wall_s": wall, "applies": applies, "info": info, "per_k": per_k, "trace": tr, "probs": p,
             "tuned_ms": tuned_ms[1:], "variants": variants, "alternative": alternative,
             "pass_sizes": pass_sizes, "alg_flops": alg_flops, "launches": len(events) // max(steps, 1),
-            "stream_s": stream_s}, d
+            "stream_s": stream_s, "mfma_tflops": mfma_tf}, d
 
 
 def d_bytes(d):
@@ -561,6 +563,14 @@ def main():
               "paper_rule_ratio": round(len(ops) / paper_blocks, 2)}
     value = r["applies"] / r["wall_s"]
 
+    def measured_mfma(rl, rr, secs):
+        """The executed products' rate against the measured rate of the same multiplication loop
+        with nothing else in it (tanq_mfma_rate), beside the datasheet fraction."""
+        if "mfma_flops_executed" in rl and rr.get("mfma_tflops"):
+            rl["mfma_measured_TFLOPs"] = round(rr["mfma_tflops"], 2)
+            rl["mfma_frac_of_measured"] = round(rl["mfma_flops_executed"] / secs / 1e12 / rr["mfma_tflops"], 4)
+        return rl
+
     def dominant(rr, prec):
         k = max(rr["per_k"], key=lambda kk: sum(rr["per_k"][kk]))
         secs = sum(rr["per_k"][k]) / len(rr["per_k"][k])
@@ -572,8 +582,8 @@ def main():
             rl["traffic"] = measured_traffic(name)
             if rl["traffic"] is not None:
                 rl["traffic_unit"] = "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
-            return rl
-        rl = roofline(prec, k, n, secs)
+            return measured_mfma(rl, rr, secs)
+        rl = measured_mfma(roofline(prec, k, n, secs), rr, secs)
         if k in rr["variants"]:
             name = kernel_name(prec, k, rr["variants"][k])
             rl["kernel"] = name

@@ -97,6 +97,16 @@ tanq_status tanq_dm_reset(tanq_dm d);
  * is not finite.  In FP32 the factor is rounded to float. */
 tanq_status tanq_dm_scale(tanq_dm d, double factor);
 
+/* The matrix units' sustained rate on the current device, in TFLOP/s, in the shape of the
+ * pass kernels' multiplication loop (Sec. 3.2's batched GEMM on the matrix units) but with
+ * nothing else: one workgroup of eight waves per CU, each repeating 16x16x4 products of
+ * precision p (FP64, or FP32 for TANQ_F32) in three independent accumulation chains with
+ * register operands, plus the 3M combination.  This is the ceiling that kernel's products can
+ * reach on this device and clock, next to the datasheet peak.  Allocates and frees a small
+ * device buffer, uses a stream of its own and synchronises it (about 0.1 s).  E_ARG for a bad
+ * precision or a NULL pointer. */
+tanq_status tanq_mfma_rate(tanq_prec p, double* tflops);
+
 /* Number of qubits, precision, element count (4^n) and device pointer of a handle. */
 tanq_status tanq_dm_query(tanq_dm d, int* n, int* prec, uint64_t* elements, void** dev_ptr);
 

@@ -380,6 +380,14 @@ tanq_status tanq_dm_scale(tanq_dm d, double factor) {
   });
 }
 
+tanq_status tanq_mfma_rate(tanq_prec p, double* tflops) {
+  return guarded([&] {
+    check_prec(p);
+    if (!tflops) fail(TANQ_E_ARG, "tflops is NULL");
+    *tflops = mfma_rate_tflops(p);
+  });
+}
+
 tanq_status tanq_dm_query(tanq_dm d, int* n, int* prec, uint64_t* elements, void** dev_ptr) {
   return guarded([&] {
     check_dm(d);

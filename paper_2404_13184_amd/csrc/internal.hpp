@@ -163,6 +163,9 @@ void launch_gather(const void* rho, tanq_prec p, const uint64_t* idx_dev, size_t
                    hipStream_t s);
 void launch_fill_random(void* rho, int n, tanq_prec p, uint64_t seed, hipStream_t s);
 void launch_scale(void* rho, int n, tanq_prec p, double f, hipStream_t s);
+// Sustained matrix-unit rate (TFLOP/s) of the pass kernels' multiplication loop shape on the
+// current device; synchronous.
+double mfma_rate_tflops(tanq_prec p);
 
 // All-qubit sampling (tanq_sample and its variant without allocations): argument checks (also
 // returning the handle's qubit count and device), and the work itself on the caller's device

@@ -478,6 +478,94 @@ void launch_fill_random(void* rho, int n, tanq_prec p, uint64_t seed, hipStream_
   TANQ_HIP(hipGetLastError());
 }
 
+// The matrix units' sustained rate in the multiplication loop of the pass kernels, without
+// the loop's LDS traffic, barriers or memory: one workgroup of eight waves per CU (two per
+// SIMD, as the pass kernels' consumer waves), each wave repeating two column blocks of three
+// independent 16x16x4 accumulation chains over four k-steps with register operands, followed
+// by the 3M combination on the vector ALU.  Operands change every iteration so nothing is
+// hoisted; one store per thread at the end keeps the work.
+template <typename T, typename A>
+__global__ __launch_bounds__(512) void mfma_rate_kernel(T* __restrict__ out, int iters) {
+  const int lane = threadIdx.x & 63;
+  T a[12], b[8][2];
+#pragma unroll
+  for (int i = 0; i < 12; ++i) a[i] = T(1) + T(1e-7) * (T)(lane + i);
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    b[i][0] = T(1e-7) * (T)i;
+    b[i][1] = T(2e-7) * (T)i;
+  }
+  A keep = {0, 0, 0, 0};
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int blk = 0; blk < 2; ++blk) {
+      A p1 = {0, 0, 0, 0}, p2 = {0, 0, 0, 0}, p3 = {0, 0, 0, 0};
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const T br = b[blk * 4 + s][0], bi = b[blk * 4 + s][1];
+        if constexpr (sizeof(T) == 8) {
+          p1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[3 * s], br, p1, 0, 0, 0);
+          p2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[3 * s + 1], bi, p2, 0, 0, 0);
+          p3 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[3 * s + 2], br + bi, p3, 0, 0, 0);
+        } else {
+          p1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[3 * s], br, p1, 0, 0, 0);
+          p2 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[3 * s + 1], bi, p2, 0, 0, 0);
+          p3 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[3 * s + 2], br + bi, p3, 0, 0, 0);
+        }
+      }
+      keep += (p1 - p2) + (p3 - p1 - p2);
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      b[i][0] += T(1e-9);
+      b[i][1] -= T(1e-9);
+    }
+  }
+  out[(size_t)blockIdx.x * 512 + threadIdx.x] = keep[0] + keep[1] + keep[2] + keep[3];
+}
+
+double mfma_rate_tflops(tanq_prec p) {
+  constexpr int kIters = 8192;
+  const int cus = device_cu_count();
+  const size_t bytes = (size_t)cus * 512 * (p == TANQ_F64 ? 8 : 4);
+  void* out = nullptr;
+  TANQ_HIP(hipMalloc(&out, bytes));
+  hipStream_t s = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  float best = 0.f;
+  try {
+    TANQ_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    TANQ_HIP(hipEventCreate(&e0));
+    TANQ_HIP(hipEventCreate(&e1));
+    for (int rep = 0; rep < 4; ++rep) {  // the first launch warms the clocks up; keep the fastest
+      TANQ_HIP(hipEventRecord(e0, s));
+      if (p == TANQ_F64)
+        hipLaunchKernelGGL((mfma_rate_kernel<double, f64x4>), dim3(cus), dim3(512), 0, s, (double*)out, kIters);
+      else
+        hipLaunchKernelGGL((mfma_rate_kernel<float, f32x4>), dim3(cus), dim3(512), 0, s, (float*)out, kIters);
+      TANQ_HIP(hipGetLastError());
+      TANQ_HIP(hipEventRecord(e1, s));
+      TANQ_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      TANQ_HIP(hipEventElapsedTime(&ms, e0, e1));
+      if (rep > 0 && (best == 0.f || ms < best)) best = ms;
+    }
+  } catch (...) {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (s) (void)hipStreamDestroy(s);
+    (void)hipFree(out);
+    throw;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipStreamDestroy(s);
+  TANQ_HIP(hipFree(out));
+  // 8 waves x 24 products of 16 x 16 x 4 (2048 flops each) per iteration
+  const double flops = (double)cus * 8.0 * kIters * 24.0 * 2048.0;
+  return flops / (best * 1e-3) / 1e12;
+}
+
 void launch_scale(void* rho, int n, tanq_prec p, double f, hipStream_t s) {
   constexpr int U = 4;
   // 16-byte accesses: one FP64 complex element, or two FP32 ones

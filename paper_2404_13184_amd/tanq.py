@@ -38,6 +38,7 @@ EXPORTED = [
     "tanq_last_error", "tanq_version",
     "tanq_dm_init", "tanq_dm_wrap", "tanq_dm_free", "tanq_dm_reset", "tanq_dm_query",
     "tanq_dm_read", "tanq_dm_write", "tanq_dm_fill_random", "tanq_dm_gather", "tanq_sync", "tanq_dm_scale",
+    "tanq_mfma_rate",
     "tanq_circuit_create", "tanq_circuit_free", "tanq_circuit_add_gate", "tanq_circuit_add_kraus",
     "tanq_circuit_add_ops", "tanq_circuit_size",
     "tanq_fuse", "tanq_fuse_plan", "tanq_fused_info", "tanq_fused_free", "tanq_fused_get",
@@ -158,6 +159,7 @@ _SIGS = {
     "tanq_expect_pauli_batch": ([_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_char_p), _dp, _dp], ctypes.c_int),
     "tanq_dm_compare": ([_vp, _vp, _dp], ctypes.c_int),
     "tanq_dm_scale": ([_vp, ctypes.c_double], ctypes.c_int),
+    "tanq_mfma_rate": ([ctypes.c_int, _dp], ctypes.c_int),
     "tanq_server_create": ([ctypes.POINTER(ServerConfig), ctypes.POINTER(_vp)], ctypes.c_int),
     "tanq_server_submit": ([_vp, _vp, ctypes.POINTER(Outputs), ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
     "tanq_server_poll": ([_vp, ctypes.c_uint64, ctypes.POINTER(Result)], ctypes.c_int),
@@ -240,6 +242,13 @@ def tanq_dm_reset(h: int):
 
 def tanq_dm_scale(h: int, factor: float):
     _check(load().tanq_dm_scale(h, float(factor)))
+
+
+def tanq_mfma_rate(prec) -> float:
+    """Sustained matrix-unit rate (TFLOP/s) of the pass kernels' multiplication loop shape."""
+    v = ctypes.c_double()
+    _check(load().tanq_mfma_rate(_prec(prec), ctypes.byref(v)))
+    return v.value
 
 
 def tanq_dm_query(h: int):

@@ -1,6 +1,7 @@
 """C-ABI checks that need no GPU: the library loads and exports every declared symbol,
 host-side argument validation, and the fusion planner (Sec. 3.3) produces an exact
 reordering of the circuit, judged by the CPU oracle."""
+import ctypes
 import os
 import re
 
@@ -303,3 +304,12 @@ def test_server_cancel_rejects_null(lib):
     import ctypes
 
     assert lib.tanq_server_cancel(None, ctypes.c_uint64(1)) == T.TANQ_E_ARG
+
+
+def test_mfma_rate_rejects_bad_arguments(lib):
+    """Argument errors come back before any device work."""
+    with pytest.raises(T.TanqError):
+        T._check(T.load().tanq_mfma_rate(0, None))
+    v = ctypes.c_double()
+    with pytest.raises(T.TanqError):
+        T._check(T.load().tanq_mfma_rate(7, ctypes.byref(v)))

@@ -409,6 +409,15 @@ def test_three_qubit_operations_fused(oracle_mod, prec):
 # in-place scaling (the plain streaming pass over the state)
 # ---------------------------------------------------------------------------------------
 
+
+@pytest.mark.parametrize("prec,peak", [("f64", 78.6), ("f32", 157.3)])
+def test_mfma_rate_is_plausible(prec, peak):
+    """The measured matrix-unit rate of the multiplication loop alone lies below the datasheet
+    peak (products of 16 x 16 x 4 at the chip's top clock) and well above a quarter of it."""
+    say("mfma rate %s" % prec)
+    r = T.tanq_mfma_rate(prec)
+    assert 0.25 * peak < r <= 1.02 * peak, r
+
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("n", [1, 2, 4, 5, 9, 12])
 def test_scale_in_place(prec, n):
