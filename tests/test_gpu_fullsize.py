@@ -180,3 +180,34 @@ def test_largest_register_fp32(oracle_mod, qubits):
             idx = (np.uint64(rf) + dep)[:, None] + ((np.uint64(cf) + dep)[None, :] << np.uint64(n))
             got = d.gather(idx.reshape(-1)).astype(np.complex128).reshape(1 << k, 1 << k)
             assert np.abs(got - M_out).max() <= 2e-5 * max(1.0, np.abs(M_out).max()), (rf, cf)
+
+
+def test_largest_register_fp32_pass(oracle_mod):
+    """n = 17 FP32 through the multi-superoperator pass kernel: five 2-qubit channels on qubits
+    {0, 13, 14, 15, 16} (one pass; tile offsets and element indices beyond 2^32), sampled
+    32 x 32 blocks against the oracle applying the same channels in order."""
+    n = 17
+    rng = np.random.default_rng(1717)
+    ops = [random_channel(rng, q) for q in ((16, 15), (14, 13), (0, 16), (16, 13), (15, 14))]
+    seed = 4
+    say("n=17 f32 pass")
+    c = T.Circuit(n, ops)
+    f = c.fuse(2, "f32")
+    assert f.passes() == (1, 5)
+    with T.DM(n, "f32") as d:
+        d.fill_random(seed)
+        d.apply_fused(f)
+        Q = [0, 13, 14, 15, 16]
+        frees = [q for q in range(n) if q not in Q]
+        vals = lambda idx: W.hash_fill_values(seed, idx).astype(np.complex64).astype(np.complex128)
+        for _ in range(8):
+            rf = sum(int(rng.integers(0, 2)) << q for q in frees)
+            cf = sum(int(rng.integers(0, 2)) << q for q in frees)
+            Qs, _, M_out = oracle_mod.sample_block(vals, n, ops, rf, cf)
+            assert Qs == Q
+            dep = np.array([sum(((a >> t) & 1) << Q[t] for t in range(5)) for a in range(32)], dtype=np.uint64)
+            idx = (np.uint64(rf) + dep)[:, None] + ((np.uint64(cf) + dep)[None, :] << np.uint64(n))
+            got = d.gather(idx.reshape(-1)).astype(np.complex128).reshape(32, 32)
+            assert np.abs(got - M_out).max() <= 5e-5 * max(1.0, np.abs(M_out).max()), (rf, cf)
+    f.free()
+    c.free()
