@@ -28,6 +28,7 @@ FP32_PEAK_TFLOPS = 157.3
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "apply_kernel_traffic_16q.txt")
+TRAFFIC_N = 16  # qubits of the state the traffic summary was taken on
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2404_13184_amd", "csrc", f) for f in ("apply.hip", "tile.hpp", "pass.hip")]
 # multi-superoperator pass kernels, by precision
 PASS_KERNELS = {"f64": "apply_pass_ws_kernel<double, 12, 640, 2>", "f32": "apply_pass_ws_kernel<float, 13, 640, 2>"}
@@ -50,11 +51,12 @@ def kernel_name(prec, k, variant) -> str:
     return "apply_tiles_kernel<%s, %d, %d, %d, true>" % (t, k, variant["tile_bits"], variant["threads"])
 
 
-def measured_traffic(name: str):
+def measured_traffic(name: str, n: int = TRAFFIC_N):
     """HBM bytes per launch of `name` from the committed rocprofv3 counter summary (FETCH_SIZE
     and WRITE_SIZE, each scaled by what the counter reads for a copy kernel of known size), or
-    None when there is no summary for it or the kernel sources changed since it was taken."""
-    if not os.path.exists(TRAFFIC_FILE):
+    None when there is no summary for it, the kernel sources changed since it was taken, or
+    the state size differs from the summary's (TRAFFIC_N qubits)."""
+    if n != TRAFFIC_N or not os.path.exists(TRAFFIC_FILE):
         return None
     src_hash, rows = None, {}
     with open(TRAFFIC_FILE) as fh:
@@ -579,7 +581,7 @@ def main():
                                sum(rr["alg_flops"][k]) / len(rr["alg_flops"][k]))
             name = PASS_KERNELS[prec]
             rl["kernel"] = name
-            rl["traffic"] = measured_traffic(name)
+            rl["traffic"] = measured_traffic(name, n)
             if rl["traffic"] is not None:
                 rl["traffic_unit"] = "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
             return measured_mfma(rl, rr, secs)
@@ -587,7 +589,7 @@ def main():
         if k in rr["variants"]:
             name = kernel_name(prec, k, rr["variants"][k])
             rl["kernel"] = name
-            rl["traffic"] = measured_traffic(name)
+            rl["traffic"] = measured_traffic(name, n)
             if rl["traffic"] is not None:
                 rl["traffic_unit"] = "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
         return rl

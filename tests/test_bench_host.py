@@ -62,6 +62,9 @@ def test_traffic_lookup_follows_the_kernel_sources(tmp_path, monkeypatch):
     stale.write_text("source_hash 0000000000000000\nkernel %s 6.0e10 7.0e10 1 1 1.0 5\n" % name.replace(" ", ""))
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(stale))
     assert bench.measured_traffic(name) is None
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(good))
+    assert bench.measured_traffic(name, 16) == pytest.approx(1.3e11)
+    assert bench.measured_traffic(name, 12) is None  # the summary's bytes are for 16 qubits
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "missing.txt"))
     assert bench.measured_traffic(name) is None
 
