@@ -182,12 +182,14 @@ struct PassOps {
 
 // Producer: stream one tile into buf with direct global-to-LDS loads (lane data lands at the
 // wave's base + 16 * lane, so slot it * PT + tid receives the 16 bytes at offset off[it]).
+// The loads and the consumers' stores are marked non-temporal (cache policy 2): a pass touches
+// every element once, so nothing it moves is read again before the next pass.
 template <typename T, int PITERS, int PT>
 __device__ inline void pass_dma_tile(const T* rho, uint64_t base, const uint64_t (&off)[PITERS], u32x4* buf,
                                      int wave) {
 #pragma unroll
   for (int it = 0; it < PITERS; ++it)
-    __builtin_amdgcn_global_load_lds(rho + 2 * (base + off[it]), buf + it * PT + wave * 64, 16, 0, 0);
+    __builtin_amdgcn_global_load_lds(rho + 2 * (base + off[it]), buf + it * PT + wave * 64, 16, 0, 2);
 }
 
 template <typename T, int VMAX, int NT, int NPW>
@@ -314,7 +316,7 @@ __global__ __launch_bounds__(NT) void apply_pass_ws_kernel(T* __restrict__ rho, 
       if (g.m & 1) ops[0] = ops[1];  // the last superoperator left superoperator 0 in ops[m & 1]
 #pragma unroll
       for (int it = 0; it < CITERS; ++it)
-        *reinterpret_cast<u32x4*>(rho + 2 * (cur + (off_ct ^ soff[it]))) = buf[it * CT + ct];
+        __builtin_nontemporal_store(buf[it * CT + ct], reinterpret_cast<u32x4*>(rho + 2 * (cur + (off_ct ^ soff[it]))));
       raw_barrier();  // B_free: this buffer is read out
       if (!more) break;
       raw_barrier();  // B0: next tile ready
