@@ -21,7 +21,7 @@ __device__ inline void batch_tiles(T* __restrict__ rho, const IO& io, const Op& 
   u32x4 buf[IO::ITERS];
 #pragma unroll
   for (int it = 0; it < IO::ITERS; ++it)
-    if (io.template has<FULL>(it, tid)) buf[it] = *reinterpret_cast<const u32x4*>(rho + 2 * (cur + io.off[it]));
+    if (io.template has<FULL>(it, tid)) buf[it] = *global_ptr(reinterpret_cast<const u32x4*>(rho + 2 * (cur + io.off[it])));
 #pragma unroll
   for (int it = 0; it < IO::ITERS; ++it)
     if (io.template has<FULL>(it, tid)) lds[io.lslot[it]] = buf[it];
@@ -34,7 +34,7 @@ __device__ inline void batch_tiles(T* __restrict__ rho, const IO& io, const Op& 
 #pragma unroll
       for (int it = 0; it < IO::ITERS; ++it)
         if (io.template has<FULL>(it, tid))
-          buf[it] = *reinterpret_cast<const u32x4*>(rho + 2 * (nbase + io.off[it]));
+          buf[it] = *global_ptr(reinterpret_cast<const u32x4*>(rho + 2 * (nbase + io.off[it])));
     }
     if constexpr (std::is_same_v<Op, Op2<T, Op::kVmax, Op::kThreads>>)
       op.template compute<FULL>(reinterpret_cast<T*>(lds), g, lane, wave);
@@ -43,7 +43,7 @@ __device__ inline void batch_tiles(T* __restrict__ rho, const IO& io, const Op& 
     lds_barrier();
 #pragma unroll
     for (int it = 0; it < IO::ITERS; ++it)
-      if (io.template has<FULL>(it, tid)) *reinterpret_cast<u32x4*>(rho + 2 * (cur + io.off[it])) = lds[io.lslot[it]];
+      if (io.template has<FULL>(it, tid)) *global_ptr(reinterpret_cast<u32x4*>(rho + 2 * (cur + io.off[it]))) = lds[io.lslot[it]];
     lds_barrier();  // every store-phase LDS read is done before the next tile lands (or the next chunk)
     if (!more) break;
 #pragma unroll
@@ -68,7 +68,7 @@ __device__ inline void batch_tiles_oop(T* __restrict__ rho, const IO& io, const 
   u32x4 buf[IO::ITERS];
 #pragma unroll
   for (int it = 0; it < IO::ITERS; ++it)
-    if (io.template has<FULL>(it, tid)) buf[it] = *reinterpret_cast<const u32x4*>(rho + 2 * (cur + io.off[it]));
+    if (io.template has<FULL>(it, tid)) buf[it] = *global_ptr(reinterpret_cast<const u32x4*>(rho + 2 * (cur + io.off[it])));
 #pragma unroll
   for (int it = 0; it < IO::ITERS; ++it)
     if (io.template has<FULL>(it, tid)) in[io.lslot[it]] = buf[it];
@@ -81,13 +81,13 @@ __device__ inline void batch_tiles_oop(T* __restrict__ rho, const IO& io, const 
 #pragma unroll
       for (int it = 0; it < IO::ITERS; ++it)
         if (io.template has<FULL>(it, tid))
-          buf[it] = *reinterpret_cast<const u32x4*>(rho + 2 * (nbase + io.off[it]));
+          buf[it] = *global_ptr(reinterpret_cast<const u32x4*>(rho + 2 * (nbase + io.off[it])));
     }
     op.template compute_to<FULL>(reinterpret_cast<const c2*>(in), reinterpret_cast<c2*>(out), g, lane, wave);
     lds_barrier();  // results complete; `in` is no longer read
 #pragma unroll
     for (int it = 0; it < IO::ITERS; ++it)
-      if (io.template has<FULL>(it, tid)) *reinterpret_cast<u32x4*>(rho + 2 * (cur + io.off[it])) = out[io.lslot[it]];
+      if (io.template has<FULL>(it, tid)) *global_ptr(reinterpret_cast<u32x4*>(rho + 2 * (cur + io.off[it]))) = out[io.lslot[it]];
     if (more) {
 #pragma unroll
       for (int it = 0; it < IO::ITERS; ++it)

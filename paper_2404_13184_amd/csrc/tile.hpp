@@ -38,6 +38,16 @@ struct Mfma<float> {
   }
 };
 
+// Device memory reached through a pointer read from memory (a work-list entry): the compiler
+// cannot tell which memory it points to and accesses it with flat instructions, which also
+// count on the LDS counter, so every wait for an LDS read would also wait for them (the next
+// tile's prefetch then no longer overlaps the multiplication).  Accesses through the returned
+// pointer are global-memory instructions.
+template <typename T>
+__device__ inline __attribute__((address_space(1))) T* global_ptr(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+
 __device__ inline uint32_t pdep32(uint32_t x, uint32_t mask) {
   uint32_t r = 0;
   for (uint32_t m = mask; m; m &= m - 1) {
@@ -213,7 +223,8 @@ struct Op2 {
   uint32_t tj1, tq;
   int nblk;
 
-  __device__ inline void load(const T* __restrict__ frag, int lane) {
+  __device__ inline void load(const T* __restrict__ frag_in, int lane) {
+    const auto* frag = global_ptr(frag_in);  // device operands (kernel argument or work list)
 #pragma unroll
     for (int m = 0; m < MT; ++m)
 #pragma unroll
@@ -301,7 +312,8 @@ struct Op3 {
   uint32_t tjk, trow0, tjm;
   int nblk;
 
-  __device__ inline void load(const T* __restrict__ frag, int lane, int wave) {
+  __device__ inline void load(const T* __restrict__ frag_in, int lane, int wave) {
+    const auto* frag = global_ptr(frag_in);  // device operands (kernel argument or work list)
     const int mt = wave & 3;
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
