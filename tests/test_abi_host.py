@@ -1,6 +1,6 @@
 """C-ABI checks that need no GPU: the library loads and exports every declared symbol,
 host-side argument validation, and the fusion planner (Sec. 3.3) produces an exact
-reordering of the circuit, judged by the CPU oracle."""
+reordering of the circuit, checked against the CPU oracle."""
 import ctypes
 import os
 import re
