@@ -11,13 +11,45 @@
 
 namespace tanq {
 
+// The run table of the current item (the tile id -> global offset map), read once per item
+// from its geometry in LDS into scalar registers: the single-state kernels have it in their
+// kernel arguments, here it would otherwise be re-read from LDS for every tile.
+struct BatchRuns {
+  uint32_t src[2], len[2], dst[2];  // run r's byte r % 4 of word r / 4
+  int32_t n;
+
+  template <typename G>
+  __device__ inline void load(const G& g) {
+#pragma unroll
+    for (int w = 0; w < 2; ++w) {
+      src[w] = (uint32_t)__builtin_amdgcn_readfirstlane((int)reinterpret_cast<const uint32_t*>(g.run_src)[w]);
+      len[w] = (uint32_t)__builtin_amdgcn_readfirstlane((int)reinterpret_cast<const uint32_t*>(g.run_len)[w]);
+      dst[w] = (uint32_t)__builtin_amdgcn_readfirstlane((int)reinterpret_cast<const uint32_t*>(g.run_dst)[w]);
+    }
+    n = __builtin_amdgcn_readfirstlane(g.nruns);
+  }
+
+  // the same map as tile_base(g, tile)
+  __device__ inline uint64_t base(uint64_t tile) const {
+    uint64_t b = 0;
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+      if (r < n) {
+        const uint32_t sh = 8 * (r % 4);
+        const uint32_t rs = (src[r / 4] >> sh) & 0xffu, rl = (len[r / 4] >> sh) & 0xffu, rd = (dst[r / 4] >> sh) & 0xffu;
+        b |= ((tile >> rs) & ((1ull << rl) - 1ull)) << rd;
+      }
+    return b;
+  }
+};
+
 // The tiles [t0, t1) of one item, in place: the next tile is prefetched into registers while
 // the current one is multiplied in LDS, as in the single-state kernel.
 template <bool FULL, typename T, typename IO, typename Op, typename G>
-__device__ inline void batch_tiles(T* __restrict__ rho, const IO& io, const Op& op, const G& g, u32x4* lds,
-                                   uint32_t t0, uint32_t t1, int tid, int lane, int wave) {
+__device__ inline void batch_tiles(T* __restrict__ rho, const IO& io, const Op& op, const G& g, const BatchRuns& runs,
+                                   u32x4* lds, uint32_t t0, uint32_t t1, int tid, int lane, int wave) {
   using c2 = typename Mfma<T>::c2;
-  uint64_t cur = tile_base(g, t0);
+  uint64_t cur = runs.base(t0);
   u32x4 buf[IO::ITERS];
 #pragma unroll
   for (int it = 0; it < IO::ITERS; ++it)
@@ -30,7 +62,7 @@ __device__ inline void batch_tiles(T* __restrict__ rho, const IO& io, const Op& 
     const bool more = t + 1 < t1;
     uint64_t nbase = 0;
     if (more) {
-      nbase = tile_base(g, t + 1);
+      nbase = runs.base(t + 1);
 #pragma unroll
       for (int it = 0; it < IO::ITERS; ++it)
         if (io.template has<FULL>(it, tid))
@@ -61,10 +93,11 @@ __device__ inline void batch_tiles(T* __restrict__ rho, const IO& io, const Op& 
 // store of `out` and the refill of `in` with the next tile (prefetched into registers), and a
 // second one the refill from the next multiplication.
 template <bool FULL, typename T, typename IO, typename Op, typename G>
-__device__ inline void batch_tiles_oop(T* __restrict__ rho, const IO& io, const Op& op, const G& g, u32x4* in,
-                                       u32x4* out, uint32_t t0, uint32_t t1, int tid, int lane, int wave) {
+__device__ inline void batch_tiles_oop(T* __restrict__ rho, const IO& io, const Op& op, const G& g,
+                                       const BatchRuns& runs, u32x4* in, u32x4* out, uint32_t t0, uint32_t t1, int tid,
+                                       int lane, int wave) {
   using c2 = typename Mfma<T>::c2;
-  uint64_t cur = tile_base(g, t0);
+  uint64_t cur = runs.base(t0);
   u32x4 buf[IO::ITERS];
 #pragma unroll
   for (int it = 0; it < IO::ITERS; ++it)
@@ -77,7 +110,7 @@ __device__ inline void batch_tiles_oop(T* __restrict__ rho, const IO& io, const 
     const bool more = t + 1 < t1;
     uint64_t nbase = 0;
     if (more) {
-      nbase = tile_base(g, t + 1);
+      nbase = runs.base(t + 1);
 #pragma unroll
       for (int it = 0; it < IO::ITERS; ++it)
         if (io.template has<FULL>(it, tid))
@@ -134,6 +167,7 @@ __global__ __launch_bounds__(NT, (BatchMinBlocks<T, K>::value)) void batch_apply
   bool full = false;
   IO io;
   Op op;
+  BatchRuns runs;
   T* rho = nullptr;
   for (;;) {
     // dynamic assignment: each workgroup claims the next chunk (count[1], zeroed by the copy of
@@ -158,20 +192,21 @@ __global__ __launch_bounds__(NT, (BatchMinBlocks<T, K>::value)) void batch_apply
       else
         op.load(frag, lane, wave);
       op.prepare(sg, lane, wave);
+      runs.load(sg);
       full = __builtin_amdgcn_readfirstlane(sg.V) == VMAX;
       cur = ch.item;
     }
     if (ch.tile_begin >= ch.tile_end) continue;
     if constexpr (kOop) {
       if (full)
-        batch_tiles_oop<true, T>(rho, io, op, sg, lds, lds2, ch.tile_begin, ch.tile_end, tid, lane, wave);
+        batch_tiles_oop<true, T>(rho, io, op, sg, runs, lds, lds2, ch.tile_begin, ch.tile_end, tid, lane, wave);
       else
-        batch_tiles_oop<false, T>(rho, io, op, sg, lds, lds2, ch.tile_begin, ch.tile_end, tid, lane, wave);
+        batch_tiles_oop<false, T>(rho, io, op, sg, runs, lds, lds2, ch.tile_begin, ch.tile_end, tid, lane, wave);
     } else {
       if (full)
-        batch_tiles<true, T>(rho, io, op, sg, lds, ch.tile_begin, ch.tile_end, tid, lane, wave);
+        batch_tiles<true, T>(rho, io, op, sg, runs, lds, ch.tile_begin, ch.tile_end, tid, lane, wave);
       else
-        batch_tiles<false, T>(rho, io, op, sg, lds, ch.tile_begin, ch.tile_end, tid, lane, wave);
+        batch_tiles<false, T>(rho, io, op, sg, runs, lds, ch.tile_begin, ch.tile_end, tid, lane, wave);
     }
   }
 }
