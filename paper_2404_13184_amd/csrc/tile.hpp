@@ -310,7 +310,23 @@ struct Op3 {
   uint32_t gj[NBW], xg[NBW];
   bool act[NBW];
   uint32_t tjk, trow0, tjm;
+  // tile-local offsets of local-index bits 2-5 (tj[4], tj[8], tj[16], tj[32]) and of bits 0-1
+  // (tj[1], tj[2]), the same in every lane: tj is linear in the local index (disjoint bits),
+  // so every tj[4 s] and output-row offset is a sum of these, formed in scalar registers
+  // rather than read from the geometry for every tile (in LDS, in the batched kernel)
+  uint32_t tb[4], tl[2];
   int nblk;
+
+  // tj[4 s]
+  __device__ inline uint32_t tk(int s) const {
+    return ((s & 1) ? tb[0] : 0u) + ((s & 2) ? tb[1] : 0u) + ((s & 4) ? tb[2] : 0u) + ((s & 8) ? tb[3] : 0u);
+  }
+  // tile-local offset of accumulator value r's output row within a k-step: tj[4 r] (FP64,
+  // rows kk + 4 r) or tj[r] (FP32, rows 4 kk + r)
+  __device__ inline uint32_t trow_of(int r) const {
+    if constexpr (M::kRowsStrided) return ((r & 1) ? tb[0] : 0u) + ((r & 2) ? tb[1] : 0u);
+    return ((r & 1) ? tl[0] : 0u) + ((r & 2) ? tl[1] : 0u);
+  }
 
   __device__ inline void load(const T* __restrict__ frag_in, int lane, int wave) {
     const auto* frag = global_ptr(frag_in);  // device operands (kernel argument or work list)
@@ -332,6 +348,10 @@ struct Op3 {
     trow0 = M::kRowsStrided ? g.tj[kk] : g.tj[4 * kk];   // output row kk + 4r (f64), 4kk + r (f32)
     tjm = g.tj[16 * (wave & 3)];                         // this wave's output m-tile
 #pragma unroll
+    for (int b = 0; b < 4; ++b) tb[b] = (uint32_t)__builtin_amdgcn_readfirstlane((int)g.tj[4 << b]);
+    tl[0] = (uint32_t)__builtin_amdgcn_readfirstlane((int)g.tj[1]);
+    tl[1] = (uint32_t)__builtin_amdgcn_readfirstlane((int)g.tj[2]);
+#pragma unroll
     for (int i = 0; i < NBW; ++i) {
       const int gi = (part + i * NPART) * 16 + (lane & 15);
       act[i] = gi < GG;
@@ -352,7 +372,7 @@ struct Op3 {
       // inactive lanes (partial tiles only) read group 0, which is in the tile, and write nothing
 #pragma unroll
       for (int s = 0; s < KS; ++s) {
-        const uint32_t e = ((g.tj[4 * s] + tjk) ^ xg[i]) + gj[i];
+        const uint32_t e = ((tk(s) + tjk) ^ xg[i]) + gj[i];
         const c2 v = in[e];
         const T br = v[0], bi = v[1];
         p1 = M::mma(ar[s], br, p1);
@@ -362,7 +382,7 @@ struct Op3 {
       if (FULL || act[i]) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const uint32_t trow = trow0 + (M::kRowsStrided ? g.tj[4 * r] : g.tj[r]);
+          const uint32_t trow = trow0 + trow_of(r);
           const uint32_t e = ((tjm + trow) ^ xg[i]) + gj[i];
           out[e] = c2{p1[r] - p2[r], p3[r] - p1[r] - p2[r]};
         }
@@ -383,7 +403,7 @@ struct Op3 {
         // inactive lanes (partial tiles only) read group 0, which is in the tile, and write nothing
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
-          const uint32_t e = ((g.tj[4 * s] + tjk) ^ xg[i]) + gj[i];
+          const uint32_t e = ((tk(s) + tjk) ^ xg[i]) + gj[i];
           const c2 v = ldsC[e];
           const T br = v[0], bi = v[1];
           const T bs = br + bi;
@@ -399,7 +419,7 @@ struct Op3 {
       if ((FULL || part + i * NPART < nblk) && act[i]) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const uint32_t trow = trow0 + (M::kRowsStrided ? g.tj[4 * r] : g.tj[r]);
+          const uint32_t trow = trow0 + trow_of(r);
           const uint32_t e = ((tjm + trow) ^ xg[i]) + gj[i];
           const T re = p1[i][r] - p2[i][r];
           const T im = p3[i][r] - p1[i][r] - p2[i][r];
