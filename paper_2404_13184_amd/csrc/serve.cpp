@@ -117,7 +117,11 @@ struct ServeRequest {
 };
 
 constexpr int kServeMaxN = 14;
-constexpr uint64_t kChunksPerItem = 256;  // chunk-list capacity per slot and step
+// Chunk-list capacity per slot and step.  The whole work list (every step's items and chunk
+// capacity) is copied to the device before each iteration's launches, so its size is on the
+// serving path: 64 per slot (4096 chunks per step at 64 slots, 0.7 MiB per 8-step iteration)
+// rather than 256 (2.2 MiB); the chunker makes chunks coarser when a step would exceed it.
+constexpr uint64_t kChunksPerItem = 64;
 constexpr uint64_t kMinChunkTiles = 4;    // smallest chunk (guided sizes shrink towards it)
 
 static size_t state_bytes(int n, tanq_prec p) { return ((size_t)1 << (2 * n)) * elem_size(p); }
