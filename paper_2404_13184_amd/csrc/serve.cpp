@@ -107,6 +107,10 @@ struct ServeRequest {
   bool finishing = false;  // its reductions are queued; leaves the resident set
   tanq_status drop = TANQ_OK;  // TANQ_E_CANCELED / TANQ_E_TIMEOUT: stop and free it, no outputs
   bool outputs_queued = false; // its reductions were queued (a later cancel no longer applies)
+  // admission work (uploads, superoperators, composition, packing, state initialisation) runs
+  // on the admission stream; the request joins the batched steps once this event completed
+  hipEvent_t ready_ev = nullptr;
+  bool ready = false;
   double deadline = 0;         // server clock time after which it times out (0: none)
   FuseLayout layout;  // planned at submit (exact footprint); consumed at admission
   // results
@@ -141,7 +145,8 @@ using namespace tanq;
 struct tanq_server_s {
   tanq_server_config cfg{};
   int device = 0;
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;      // batched launches, reductions, result copies
+  hipStream_t adm_stream = nullptr;  // admission: fusion kernels and state initialisation
   std::chrono::steady_clock::time_point t0;
 
   // device and pinned memory
@@ -279,16 +284,22 @@ void tanq_server_s::admit_one(ServeRequest* r) {
   std::memcpy(stg, L.ops.data(), L.ops.size() * sizeof(FuseOpDev));
   std::memcpy(stg + ops_b, L.blocks.data(), L.blocks.size() * sizeof(FuseBlockDev));
   std::memcpy(stg + ops_b + blk_b, L.kraus.data(), L.kraus.size() * sizeof(double));
-  TANQ_HIP(hipMemcpyAsync(tmp, stg, stage_size, hipMemcpyHostToDevice, stream));
+  TANQ_HIP(hipMemcpyAsync(tmp, stg, stage_size, hipMemcpyHostToDevice, adm_stream));
   hipEvent_t ev = get_event();
-  TANQ_HIP(hipEventRecord(ev, stream));
+  TANQ_HIP(hipEventRecord(ev, adm_stream));
   staged.push_back({ev, stage_off, stage_size});
   run_fuse_kernels(L, (const FuseOpDev*)tmp, (const FuseBlockDev*)(tmp + ops_b), (const double*)(tmp + ops_b + blk_b),
                    (double*)(tmp + ops_b + blk_b + kr_b), (double*)(tmp + ops_b + blk_b + kr_b + sop_b),
-                   arena_base + keep_off + rho_b, p, stream);
-  // single stream: later work that reuses this region is ordered after the fusion kernels
+                   arena_base + keep_off + rho_b, p, adm_stream);
+  // every later user of this region is ordered after the fusion kernels: other admissions run
+  // on the same stream, and only admissions allocate from the arena
   arena.release(tmp_off, tmp_size);
-  launch_init_zero(arena_base + r->rho_off, r->n, p, stream);
+  launch_init_zero(arena_base + r->rho_off, r->n, p, adm_stream);
+  // the batched launches (on the other stream) take the request only once this has completed,
+  // checked on the host, so they never wait on the admission stream
+  r->ready_ev = get_event();
+  TANQ_HIP(hipEventRecord(r->ready_ev, adm_stream));
+  r->ready = false;
 
   r->pack_off.resize(L.host.size());
   r->geom.resize(L.host.size());
@@ -327,6 +338,19 @@ void tanq_server_s::run_iteration() {
     }
     rr_next = (rr_next + cohort.size()) % active.size();
   }
+  // requests whose admission work has not completed yet sit this iteration out (and cannot be
+  // dropped or finished yet: their memory is still being written on the admission stream)
+  for (ServeRequest* r : active)
+    if (!r->ready) {
+      const hipError_t q = hipEventQuery(r->ready_ev);
+      if (q == hipErrorNotReady) continue;
+      TANQ_HIP(q);
+      put_event(r->ready_ev);
+      r->ready_ev = nullptr;
+      r->ready = true;
+    }
+  cohort.erase(std::remove_if(cohort.begin(), cohort.end(), [](ServeRequest* r) { return !r->ready; }),
+               cohort.end());
   // dropped requests (cancelled or timed out) leave now: no further applies, no outputs; the
   // event recorded after this iteration's launches orders the release of their memory after
   // every launch already queued for them
@@ -336,7 +360,7 @@ void tanq_server_s::run_iteration() {
     for (ServeRequest* r : active)
       if (!r->finishing && r->drop == TANQ_OK && r->deadline > 0 && t > r->deadline) r->drop = TANQ_E_TIMEOUT;
     for (ServeRequest* r : active)
-      if (!r->finishing && r->drop != TANQ_OK) {
+      if (r->ready && !r->finishing && r->drop != TANQ_OK) {
         r->finishing = true;
         done_now.push_back(r);
       }
@@ -349,6 +373,7 @@ void tanq_server_s::run_iteration() {
       r->finishing = true;
       done_now.push_back(r);
     }
+  bool any_item = false;  // some step has work (otherwise the launches are skipped)
   for (int s = 0; s < S; ++s) {
     uint32_t ni = 0, nc = 0;
     BatchItem* items = step_items(W, s);
@@ -401,18 +426,28 @@ void tanq_server_s::run_iteration() {
     }
     step_count(W, s)[0] = nc;
     step_count(W, s)[1] = 0;  // next unclaimed chunk, reset by the copy before each launch
+    any_item = any_item || ni > 0;
     for (uint32_t i = 0; i < ni; ++i) n_tiles += ntiles[i];
     n_chunks += nc;
     if (nc) ++n_steps;
   }
-  if (graph[b]) {
-    TANQ_HIP(hipGraphLaunch(graph[b], stream));
-  } else {
-    record_launches(b);
+  if (any_item) {
+    if (graph[b]) {
+      TANQ_HIP(hipGraphLaunch(graph[b], stream));
+    } else {
+      record_launches(b);
+    }
+    n_launches += 1;
+    TANQ_HIP(hipEventRecord(work_ev[b], stream));
+    work_ev_used[b] = true;
+  } else if (done_now.empty()) {
+    // every resident request is still being admitted: wait for the oldest instead of spinning
+    for (ServeRequest* r : active)
+      if (!r->ready) {
+        TANQ_HIP(hipEventSynchronize(r->ready_ev));
+        break;
+      }
   }
-  n_launches += 1;
-  TANQ_HIP(hipEventRecord(work_ev[b], stream));
-  work_ev_used[b] = true;
 
   if (!done_now.empty()) {
     const tanq_prec p = (tanq_prec)cfg.prec;
@@ -589,6 +624,7 @@ void tanq_server_s::loop() {
       bytes_in_use.store(arena.used());
       peak_bytes.store(arena.peak());
     }
+    TANQ_HIP(hipStreamSynchronize(adm_stream));
     TANQ_HIP(hipStreamSynchronize(stream));
     finalize_done(true);
   } catch (const std::exception& e) {
@@ -639,7 +675,10 @@ void destroy_server(tanq_server_s* s) {
     s->worker.join();
   }
   (void)hipSetDevice(s->device);
+  if (s->adm_stream) (void)hipStreamSynchronize(s->adm_stream);
   if (s->stream) (void)hipStreamSynchronize(s->stream);
+  for (auto& kv : s->all)
+    if (kv.second->ready_ev) (void)hipEventDestroy(kv.second->ready_ev);
   for (int b = 0; b < 2; ++b) {
     if (s->graph[b]) (void)hipGraphExecDestroy(s->graph[b]);
     if (s->work_ev[b]) (void)hipEventDestroy(s->work_ev[b]);
@@ -656,6 +695,7 @@ void destroy_server(tanq_server_s* s) {
   if (s->result_dev) (void)hipFree(s->result_dev);
   if (s->masks_dev) (void)hipFree(s->masks_dev);
   if (s->stream) (void)hipStreamDestroy(s->stream);
+  if (s->adm_stream) (void)hipStreamDestroy(s->adm_stream);
   delete s;
 }
 
@@ -685,6 +725,7 @@ tanq_status tanq_server_create(const tanq_server_config* cfg, tanq_server* out) 
     try {
       TANQ_HIP(hipGetDevice(&s->device));
       TANQ_HIP(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
+      TANQ_HIP(hipStreamCreateWithFlags(&s->adm_stream, hipStreamNonBlocking));
       TANQ_HIP(hipMalloc((void**)&s->arena_base, c.hbm_budget));
       s->arena.init(c.hbm_budget);
       const size_t pinned_size = 256ull << 20;
