@@ -1,10 +1,12 @@
 // Batched superoperator apply for the serving loop (gfx950): one launch applies the next fused
 // superoperator of every active request to that request's own vec(rho).  The work is a list of
 // chunks (request item, range of tiles); a persistent grid claims chunks from the list one at
-// a time (an atomic counter in the work list), stages each item's tile geometry in LDS and
-// runs the same in-place tile multiplication as the single-state kernels (tile.hpp).  States of different requests are disjoint, so the chunks of one launch
-// are independent; successive launches are ordered on the stream.  The number of chunks is read
-// from device memory, which lets a fixed launch be captured in a graph and replayed.
+// a time (an atomic counter in the work list), stages each item's tile geometry in LDS (its run
+// table and row offsets in scalar registers) and runs the same tile multiplication as the
+// single-state kernels (tile.hpp).  States of different requests are disjoint, so the chunks
+// of one launch are independent; successive launches are ordered on the stream.  The number of
+// chunks is read from device memory, which lets a fixed launch be captured in a graph and
+// replayed.
 #include <type_traits>
 
 #include "tile.hpp"
@@ -136,7 +138,8 @@ __device__ inline void batch_tiles_oop(T* __restrict__ rho, const IO& io, const 
 // Workgroups per CU the FP32 k = 3 kernel is compiled for: three (at most 168 registers per lane,
 // a few of them spilled outside the multiplication) instead of the two its unconstrained
 // allocation allows; the third workgroup's waves hide the others' barriers and tile turnovers
-// (203 against 198 circuits/s on the serving stream).  Every other shape keeps its allocation.
+// (measured on the serving stream's latency and throughput; four, at 128 registers, spills
+// inside the loop).  Every other shape keeps its allocation.
 template <typename T, int K>
 struct BatchMinBlocks { static constexpr int value = 1; };
 template <>
