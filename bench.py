@@ -31,7 +31,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "apply_kernel_traffic_16q.txt")
 TRAFFIC_N = 16  # qubits of the state the traffic summary was taken on
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2404_13184_amd", "csrc", f) for f in ("apply.hip", "tile.hpp", "pass.hip")]
 # multi-superoperator pass kernels, by precision
-PASS_KERNELS = {"f64": "apply_pass_ws_kernel<double, 12, 640, 2>", "f32": "apply_pass_ws_kernel<float, 13, 640, 2>"}
+PASS_KERNELS = {"f64": "apply_pass_kernel<double, 12, 512>", "f32": "apply_pass_ws_kernel<float, 13, 640, 2>"}
 
 
 def kernel_source_hash() -> str:
