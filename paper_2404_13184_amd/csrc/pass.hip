@@ -333,9 +333,13 @@ __global__ __launch_bounds__(NT) void apply_pass_ws_kernel(T* __restrict__ rho, 
 // wave's base: lane l fills lds_base + 16 l), with the non-temporal policy.  Written as
 // assembly because the compiler cannot tell this wave's two tile buffers apart: with the
 // builtin it would wait for every such load before each LDS read of the other buffer, which
-// removes the overlap of the next tile's loads with this tile's multiplication.  It has no
-// register outputs; the kernel waits for these loads itself (vm_wait) before the barrier that
-// publishes the tile.
+// removes the overlap of the next tile's loads with this tile's multiplication.  The
+// instruction is the one the builtin emits: its only register operand is the address, read
+// when it issues, and it has no register outputs (the data goes to LDS), so nothing the
+// compiler allocates is written while it is in flight.  The compiler does not count it, so the
+// kernel orders it itself: no LDS access touches the destination buffer until this wave has
+// waited for its loads (vm_wait) and the workgroup has passed the barrier that publishes the
+// tile, and no load is left in flight at the end of the kernel.
 __device__ inline void pass_dma16(const void* gaddr, uint32_t lds_base) {
   // M0 holds the LDS address; one wait state between writing M0 and the load that reads it
   asm volatile("s_nop 0\n\tglobal_load_lds_dwordx4 %0, off nt" ::"v"(gaddr), "{m0}"(lds_base) : "memory");
