@@ -59,14 +59,14 @@ __device__ inline uint64_t pass_tile_base(const PassGeom& g, uint64_t tile) {
 
 }  // namespace
 
-// Superoperators per specialised-wave pass: their 3M operands (768 elements each) live in LDS
-// beside the two 64 KiB tile buffers.
+// Superoperators per pass: their 3M operands (768 elements each) are rebuilt in LDS beside the
+// two 64 KiB tile buffers at the start of every launch.
 template <typename T>
-struct PassWsMax;
+struct PassMax;
 template <>
-struct PassWsMax<double> { static constexpr int M = kPassMaxF64; };
+struct PassMax<double> { static constexpr int M = kPassMaxF64; };
 template <>
-struct PassWsMax<float> { static constexpr int M = kPassMaxF32; };
+struct PassMax<float> { static constexpr int M = kPassMaxF32; };
 
 // Global offset of tile element e0 = S(first element of LDS slot p); the slot's EPS elements are
 // consecutive in the tile and in vec(rho) (tile bit 0 is global bit 0, and this swizzle never
@@ -207,7 +207,7 @@ __global__ __launch_bounds__(NT) void apply_pass_ws_kernel(T* __restrict__ rho, 
   constexpr int CITERS = SLOTS / CT;           // stores per consumer thread per tile
   static_assert(SLOTS % PT == 0 && SLOTS % CT == 0, "whole slots per thread");
   constexpr int G = 1 << (VMAX - 4);
-  constexpr int MMAX = PassWsMax<T>::M;
+  constexpr int MMAX = PassMax<T>::M;
 
   __shared__ u32x4 ldsA[SLOTS];
   __shared__ u32x4 ldsB[SLOTS];
@@ -402,7 +402,7 @@ __global__ __launch_bounds__(NT) void apply_pass_kernel(T* __restrict__ rho, con
   static_assert(SLOTS % NT == 0, "whole slots per thread");
   static_assert(ITERS < 64, "a tile's loads fit the memory counter");
   constexpr int G = 1 << (VMAX - 4);
-  constexpr int MMAX = PassWsMax<T>::M;
+  constexpr int MMAX = PassMax<T>::M;
   using Ops = PassOps<T, VMAX, NW>;
 
   __shared__ u32x4 ldsA[SLOTS];
@@ -499,7 +499,7 @@ template <typename T>
 static void launch_pass_typed(void* rho, const PassGeom& g, const void* frags, hipStream_t s) {
   constexpr int V = PassShape<T>::V, NT = PassKernel<T>::NT;
   if (g.V != V) fail(TANQ_E_STATE, "pass geometry built for another tile size");
-  if (g.m < 1 || g.m > PassWsMax<T>::M) fail(TANQ_E_STATE, "pass longer than its operand buffers");
+  if (g.m < 1 || g.m > PassMax<T>::M) fail(TANQ_E_STATE, "pass longer than its operand buffers");
   auto kern = PassKernel<T>::kern;
   static thread_local int cap_dev = -1;
   static thread_local uint64_t cap = 0;
