@@ -51,7 +51,7 @@ def test_single_apply_roofline():
 
 
 def test_traffic_lookup_follows_the_kernel_sources(tmp_path, monkeypatch):
-    name = "apply_pass_ws_kernel<double, 12, 640, 2>"
+    name = "apply_pass_kernel<double, 12, 512>"
     good = tmp_path / "good.txt"
     good.write_text("# summary\nsource_hash %s\nkernel %s 6.0e10 7.0e10 1 1 1.0 5\n"
                     % (bench.kernel_source_hash(), name.replace(" ", "")))
