@@ -59,6 +59,18 @@ __device__ inline uint64_t pass_tile_base(const PassGeom& g, uint64_t tile) {
 
 }  // namespace
 
+// Tiles of one workgroup of a pass launch: a contiguous range of ceil(ntiles / gridDim.x)
+// tiles (the last ranges shorter or empty), so that consecutive tiles of a CU lie next to each
+// other in vec(rho) instead of a grid apart.
+struct PassTiles {
+  uint64_t first, end;
+};
+__device__ inline PassTiles pass_tiles(uint64_t ntiles) {
+  const uint64_t per = (ntiles + gridDim.x - 1) / gridDim.x;
+  const uint64_t first = (uint64_t)blockIdx.x * per;
+  return PassTiles{first, first + per < ntiles ? first + per : ntiles};
+}
+
 // Superoperators per pass: their 3M operands (768 elements each) are rebuilt in LDS beside the
 // two 64 KiB tile buffers at the start of every launch.
 template <typename T>
@@ -226,8 +238,9 @@ __global__ __launch_bounds__(NT) void apply_pass_ws_kernel(T* __restrict__ rho, 
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
 
-  uint64_t tile = xcd_first_tile();
-  if (tile >= g.ntiles) return;  // uniform per workgroup
+  const PassTiles range = pass_tiles(g.ntiles);
+  uint64_t tile = range.first;
+  if (tile >= range.end) return;  // uniform per workgroup
   for (int idx = tid; idx < g.m * kOp3M; idx += NT)
     opl[idx / kOp3M][idx % kOp3M] = pass_op3m<T>(frags + g.op_off[idx / kOp3M], idx % kOp3M);
   if (tid < CITERS) soff[tid] = pass_slot_off<T, VMAX>((uint32_t)(tid * CT * EPS), g);
@@ -254,8 +267,8 @@ __global__ __launch_bounds__(NT) void apply_pass_ws_kernel(T* __restrict__ rho, 
     vm_wait<0>();
     raw_barrier();  // B0: first tile ready
     for (int t = 0;; ++t) {
-      const uint64_t next = tile + gridDim.x;
-      const bool more = next < g.ntiles;
+      const uint64_t next = tile + 1;
+      const bool more = next < range.end;
       if (more) {
         // tbase[(t + 1) & 1] was last read before this tile's B0
         const uint64_t base = pass_tile_base(g, next);
@@ -285,8 +298,8 @@ __global__ __launch_bounds__(NT) void apply_pass_ws_kernel(T* __restrict__ rho, 
     raw_barrier();  // B0: first tile ready
     for (int t = 0;; ++t) {
       const uint64_t cur = tbase[t & 1];
-      const uint64_t next = tile + gridDim.x;
-      const bool more = next < g.ntiles;
+      const uint64_t next = tile + 1;
+      const bool more = next < range.end;
       u32x4* buf = (t & 1) ? ldsB : ldsA;
       c2* bufC = reinterpret_cast<c2*>(buf);
 #pragma unroll
@@ -416,8 +429,9 @@ __global__ __launch_bounds__(NT) void apply_pass_kernel(T* __restrict__ rho, con
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
 
-  uint64_t tile = xcd_first_tile();
-  if (tile >= g.ntiles) return;  // uniform per workgroup
+  const PassTiles range = pass_tiles(g.ntiles);
+  uint64_t tile = range.first;
+  if (tile >= range.end) return;  // uniform per workgroup
   for (int idx = tid; idx < g.m * kOp3M; idx += NT)
     opl[idx / kOp3M][idx % kOp3M] = pass_op3m<T>(frags + g.op_off[idx / kOp3M], idx % kOp3M);
   if (tid < ITERS) soff[tid] = pass_slot_off<T, VMAX>((uint32_t)(tid * NT * EPS), g);
@@ -452,8 +466,8 @@ __global__ __launch_bounds__(NT) void apply_pass_kernel(T* __restrict__ rho, con
   vm_wait<0>();
   raw_barrier();  // the first tile is in LDS
   for (int t = 0;; ++t) {
-    const uint64_t next = tile + gridDim.x;
-    const bool more = next < g.ntiles;
+    const uint64_t next = tile + 1;
+    const bool more = next < range.end;
     // the other buffer was read out before the barrier that published this tile
     const uint64_t nbase = more ? pass_tile_base(g, next) : 0;
     if (t & 1)
