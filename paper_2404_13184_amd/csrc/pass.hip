@@ -5,10 +5,11 @@
 // A pass is a run of fused 2-qubit blocks whose qubits together number at most V/2 (the tile
 // holds the row and column bit of every one of them, plus the lowest other bits up to V).  For
 // each superoperator of the pass the tile splits into 2^(V-4) groups of 16 elements, indexed by
-// the tile bits that are not its targets; the multiplication of every group is exactly the one
-// the single-superoperator kernel performs (the same real-block MFMA sequence, Sec. 3.1-3.2's
-// batched GEMM), only the addresses differ.  Superoperators follow one another in circuit
-// order, separated by an LDS barrier, so the result is the same as applying them one by one.
+// the tile bits that are not its targets, and every group is multiplied by the 16 x 16 complex
+// superoperator as in the single-superoperator kernel (Sec. 3.1-3.2's batched GEMM), here in
+// 3M form (three real MFMA products instead of the real-block form's four).  Superoperators
+// follow one another in circuit order, separated by an LDS barrier, so the result is that of
+// applying them one by one, up to the rounding of the two forms.
 //
 // LDS swizzle.  One LDS layout serves every superoperator of the pass, so the swizzle is a
 // linear map over GF(2): element e lives at S(e) = e ^ X(e), where X XORs a W-bit value (W = 4
@@ -22,8 +23,9 @@
 //
 // Kernels.  One workgroup per CU and two 64 KiB LDS tile buffers: the next tile streams into
 // one with direct global-to-LDS loads while the current one is multiplied in the other and
-// stored.  FP32 (apply_pass_ws_kernel): specialised waves, two producer waves issuing the loads
-// and eight consumer waves that multiply, reading each superoperator's operands from LDS one
+// stored; each workgroup walks a contiguous range of tiles (pass_tiles).  FP32
+// (apply_pass_ws_kernel): specialised waves, two producer waves issuing the loads and eight
+// consumer waves that multiply, reading each superoperator's operands from LDS one
 // superoperator ahead.  FP64 (apply_pass_kernel): eight waves that all multiply and each issue
 // their share of the loads; two waves per SIMD leave enough registers to hold the operands of
 // all (at most four) superoperators for the whole kernel.
