@@ -459,6 +459,14 @@ __global__ __launch_bounds__(NT) void apply_pass_kernel(T* __restrict__ rho, con
 #pragma unroll
     for (int it = 0; it < ITERS; ++it) off[it] = off_t ^ soff[it];
   }
+  // The run table deposits the tile index into the global bits outside the tile, lowest first,
+  // so the base of the next tile follows from the current one by an increment under that mask
+  // (the bits outside it set so that the carry passes over them): three scalar operations per
+  // tile instead of walking the run table at the start of every tile.
+  uint64_t dmask = 0;
+#pragma unroll
+  for (int r = 0; r < 16; ++r)
+    if (r < g.nruns) dmask |= ((1ull << g.run_len[r]) - 1ull) << g.run_dst[r];
   uint64_t cur = pass_tile_base(g, tile);
   {
     const uint32_t ab = lds_addr(ldsA) + (uint32_t)wave * 1024u;
@@ -471,7 +479,7 @@ __global__ __launch_bounds__(NT) void apply_pass_kernel(T* __restrict__ rho, con
     const uint64_t next = tile + 1;
     const bool more = next < range.end;
     // the other buffer was read out before the barrier that published this tile
-    const uint64_t nbase = more ? pass_tile_base(g, next) : 0;
+    const uint64_t nbase = more ? ((cur | ~dmask) + 1ull) & dmask : 0;
     if (t & 1)
       pass_cw_tile<T, VMAX, NT, MMAX, ITERS>(rho, ops, g.m, ldsB, ldsA, cur, nbase, more, off, tid, wave);
     else
