@@ -225,7 +225,9 @@ PassGeom make_pass_geom(int n, int m, const int* qubits, const uint32_t* op_off,
     if ((b < P.W && g.xcol[b]) || (g.xcol[b] >> P.W) || (b >= V && g.xcol[b]) || (p != TANQ_F64 && (g.xcol[b] & 1u)))
       fail(TANQ_E_STATE, "pass swizzle column outside the bank window");
 
-  // runs of fixed bits
+  // runs of fixed bits: the maximal runs of global bits outside the tile, lowest first, each
+  // taking the next tile-index bits; so a tile's base is the tile index deposited into those
+  // bits, which the FP64 pass kernel relies on to step from one tile's base to the next
   int src = 0, nr = 0;
   for (int b = 0; b < nb;) {
     if ((vmask >> b) & 1ull) {
